@@ -1,0 +1,184 @@
+/*
+ * anomps.h -- C-ABI of the MI355X (gfx950) library for MPS Pauli-pair feature extraction.
+ *
+ * The library simulates the feature-extraction circuit of an adaptive non-local observable
+ * VQC on a matrix product state (§II of the paper) for a batch of images and returns the
+ * fixed two-qubit Pauli expectations that the trainable observables are built from:
+ *
+ *   image x (p x p pixels, x in [0,1], row-major site k = r*p + c)
+ *     -> product state, qubit k in R_Y(pi x_k)|0>                              (mps_init_batch)
+ *     -> L layers: R_Y(theta_k) R_Z(phi_k) on every qubit, then CNOT(k,k+1) for
+ *        k = 0..n-2, each two-site update split by an SVD that keeps at most chi
+ *        singular values (§II-B, Eq. (3))                                     (mps_apply_layer)
+ *     -> <P_a (x) P_b> on each listed pair (i, j)   (§II-C, Eq. (4)-(5))      (mps_pauli_pair_expect)
+ *     -> q_q = sum_alpha c_{q,alpha} <P_alpha>, y = W q + b   (Eq. (4)-(6))   (mps_ano_coeffs, mps_ano_readout)
+ *
+ * Conventions shared by every call:
+ *  - Ownership: every pointer argument is caller-owned.  Unless a parameter says "host", it
+ *    points to DEVICE memory of the current HIP device.  The library never allocates device
+ *    memory in these calls; it keeps only host-side tables and the message of the last error.
+ *  - Streams: every call only enqueues work on `stream` (0 = the null stream) and returns
+ *    without synchronising.  Independent batches may run on different streams.
+ *  - Errors: argument and capacity errors are detected on the host and returned before any
+ *    launch (the batch is left unchanged).  A failed launch returns MPS_ERR_HIP.  Numerical
+ *    trouble inside a kernel is reported per image in `status` (read after the stream is
+ *    synchronised).  mps_last_error() gives a message for the last non-OK return of the
+ *    calling thread.
+ *  - Pauli index: alpha = 4a + b - 1 with I,X,Y,Z = 0,1,2,3, P_a acting on the lower site i,
+ *    P_b on site j; the identity-identity term (a = b = 0) is omitted (its value is 1).
+ *  - Gates: R_Y(t) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]], R_Z(t) = diag(e^{-it/2}, e^{it/2}),
+ *    CNOT(c,t) |c,t> = |c, t XOR c>.
+ *  - Complex numbers are stored as interleaved (re, im) pairs of the precision's real type.
+ */
+#ifndef ANOMPS_H
+#define ANOMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return value of every int-returning call. */
+typedef enum {
+  MPS_OK = 0,
+  MPS_ERR_INVALID_ARG = -1, /* bad pointer, size, pair, precision or order of calls */
+  MPS_ERR_CAPACITY = -2,    /* request exceeds a documented limit (e.g. bond dimension) */
+  MPS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  MPS_ERR_UNSUPPORTED = -4  /* valid request outside what this build implements */
+} mps_status;
+
+/* Arithmetic of a batch.  FP64: complex128 state, FP64 everywhere.  FP32: complex64 state,
+ * environments, pair contractions and outputs in FP32; the SVD, the orthogonalisation of the
+ * canonical sweep and the singular-value renormalisation in FP64.  SPLIT_BF16: as FP32 but the
+ * environment and pair contractions use bf16 matrix cores on a hi+lo split of each FP32
+ * operand with FP32 accumulation. */
+typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32 = 1, MPS_PREC_SPLIT_BF16 = 2 } mps_precision;
+
+/* Per-image status word (bit flags, 0 = fine). */
+enum {
+  MPS_IMG_OK = 0,
+  MPS_IMG_NONFINITE = 1,      /* a pixel or an intermediate value was NaN/Inf */
+  MPS_IMG_NO_CONVERGENCE = 2  /* a Jacobi SVD hit its sweep limit (result still written) */
+};
+
+/* Largest bond dimension this build keeps (after the min with 2^layers and the chain ends). */
+#define MPS_MAX_BOND 16
+/* Largest number of sites. */
+#define MPS_MAX_SITES 1024
+
+/*
+ * Bond dimension after `layers` layers, between sites `bond` and `bond`+1:
+ *   D = min(chi, 2^layers, 2^(bond+1), 2^(n_sites-bond-1)).
+ * chi is the maximum virtual dimension of §II-B; each two-site update keeps
+ * min(chi, rows, cols) singular values of its (2 D_left) x (2 D_right) matrix, which gives this
+ * closed form for the CNOT-ladder circuit.  Returns 0 for out-of-range arguments.
+ */
+int32_t mps_bond_dim(int32_t n_sites, int32_t chi, int32_t layers, int32_t bond);
+
+/* Slot dimension of a batch that will receive `n_layers` layers: the largest bond dimension it
+ * will reach, max_k mps_bond_dim(n_sites, chi, n_layers, k) (at least 1). */
+int32_t mps_slot_dim(int32_t n_sites, int32_t chi, int32_t n_layers);
+
+/*
+ * Sizes in bytes of the caller-owned buffers of a batch (0 for invalid arguments).
+ *  state : [batch][n_sites][S][2][S] complex, S = mps_slot_dim(...).  Site k's tensor
+ *          A[k] (D_{k-1} x 2 x D_k) occupies the leading corner: element (a, s, b) at
+ *          ((a*2 + s)*S + b).  Entries outside the corner are never read.
+ *  env   : [batch][2][n_sites+1][S][S] complex: left environments L_0..L_n then right
+ *          environments R_0..R_n (ket index first).  Filled by mps_pauli_pair_expect.
+ */
+size_t mps_state_bytes(int32_t n_sites, int32_t chi, int32_t n_layers, int32_t batch, int32_t precision);
+size_t mps_env_bytes(int32_t n_sites, int32_t chi, int32_t n_layers, int32_t batch, int32_t precision);
+
+/* A batch of images that share n_sites, chi, the number of layers and the layer angles.
+ * Plain descriptor: the caller fills every field except layers_done, which the library
+ * maintains (set to 0 by mps_init_batch, incremented by mps_apply_layer). */
+typedef struct {
+  int32_t n_sites;    /* n = p*p qubits, 2 <= n <= MPS_MAX_SITES */
+  int32_t chi;        /* maximum bond dimension, >= 1 */
+  int32_t n_layers;   /* layers this batch will receive (sizes the slots), >= 0 */
+  int32_t batch;      /* images, >= 1 */
+  int32_t precision;  /* mps_precision */
+  int32_t layers_done;
+  void* state;        /* device, >= mps_state_bytes(...) */
+  void* env;          /* device, >= mps_env_bytes(...) */
+  int32_t* status;    /* device [batch], per-image MPS_IMG_* flags (OR-ed) */
+} mps_batch;
+
+/*
+ * Angle-encode the pixels into the product state (§II-B: one pixel per qubit, row-major):
+ * A[k] = (cos(pi x_k / 2), sin(pi x_k / 2)) as a 1 x 2 x 1 tensor.  Clears `status` and sets
+ * layers_done = 0.  pixels: device [batch][n_sites] float64 (values outside [0,1] are
+ * accepted; NaN/Inf set MPS_IMG_NONFINITE).
+ */
+int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream);
+
+/*
+ * Apply the next layer (§II-B): the one-qubit gates R_Y(theta_k) R_Z(phi_k) (updating single
+ * site tensors), then CNOT(k, k+1) for k = 0..n-2 in order, each as a two-site update: contract
+ * A[k] A[k+1], apply the CNOT, split with a one-sided Jacobi SVD in FP64, keep the
+ * min(chi, rows, cols) largest singular triplets, rescale the kept singular values to unit
+ * 2-norm, A[k] <- U (left-orthonormal), A[k+1] <- S V^dag.  Before the ladder the chain is
+ * swept right to left into right-canonical form (the one-qubit gates are applied during that
+ * sweep), so every truncation acts on Schmidt values.
+ *  theta, phi : device [n_sites] float64, this layer's angles (shared by the batch).
+ *  trunc_err  : device [batch][n_sites-1] float64 or NULL; receives the discarded weight
+ *               sum_discarded sigma^2 / sum sigma^2 of every bond of this layer.
+ * Errors: MPS_ERR_INVALID_ARG if layers_done == n_layers or the batch was not initialised.
+ */
+int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
+                    hipStream_t stream);
+
+/*
+ * Host-side check of a pair list (host pointer): 0 <= i < j < n_sites for every pair.
+ * Returns MPS_OK or MPS_ERR_INVALID_ARG (with the first offending pair in mps_last_error()).
+ */
+int mps_validate_pairs(const int32_t* pairs_host, int32_t m, int32_t n_sites);
+
+/*
+ * Two-qubit Pauli expectations on the listed pairs (§II-C, Eq. (4)-(5)):
+ *   out[b][q][4a + c - 1] = Re Tr(rho_{i_q j_q} (P_a (x) P_c)).
+ * Computes the left and right environment sweeps into b->env, then for every start site i the
+ * reduced density matrices of all pairs (i, j) by carrying the open two-layer block from i
+ * through the transfer matrices of sites i+1..j-1.  pairs: device [m][2] int32 with i < j
+ * (check the list with mps_validate_pairs; an invalid pair yields NaN outputs).  out: device
+ * [batch][m][15], float64 for MPS_PREC_FP64, float32 otherwise.  m may be 0.
+ */
+int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* out,
+                          hipStream_t stream);
+
+/*
+ * Pauli-basis coefficients of the adaptive observables (§II-A, Eq. (4)):
+ *   H_q[j][j] = D[q][j]; for the upper positions (0,1),(0,2),(0,3),(1,2),(1,3),(2,3), in this
+ *   order, H_q[j][k] = A[q][idx] + i B[q][idx] and H_q[k][j] = conj; basis |s_i s_j>.
+ *   coeff[q][4a + c] = Tr(H_q (P_a (x) P_c)) / 4, alpha = 0 the identity term.
+ * A, B: device [m][6]; D: device [m][4]; coeff: device [m][16].  Real type float64 if is_f64,
+ * float32 otherwise.
+ */
+int mps_ano_coeffs(const void* A, const void* B, const void* D, int32_t m, void* coeff,
+                   int32_t is_f64, hipStream_t stream);
+
+/*
+ * Observable-weighted linear readout (Eq. (5)-(6)):
+ *   q[b][q] = coeff[q][0] + sum_{alpha=0..14} coeff[q][alpha+1] * pauli[b][q][alpha]
+ *   y[b][o] = sum_q W[o][q] q[b][q] + bias[o]
+ * pauli: device [batch][m][15]; coeff: [m][16]; W: [out_dim][m]; bias: [out_dim] or NULL;
+ * y: [batch][out_dim].  All float64 if is_f64, else float32.  m <= 4096 (MPS_ERR_CAPACITY).
+ */
+int mps_ano_readout(const void* pauli, const void* coeff, const void* W, const void* bias,
+                    int32_t batch, int32_t m, int32_t out_dim, void* y, int32_t is_f64,
+                    hipStream_t stream);
+
+/* Message for the last non-OK return on the calling thread ("" if none).  The pointer stays
+ * valid until the next call on that thread. */
+const char* mps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANOMPS_H */

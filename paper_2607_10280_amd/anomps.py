@@ -1,0 +1,217 @@
+"""Thin Python binding of libanomps (include/anomps.h): argument marshalling only.
+
+Every computation happens in the HIP kernels of the shared library; this module only turns
+torch device tensors into pointers, the current torch stream into a hipStream_t, and non-OK
+return codes into exceptions.  There is no CPU fallback: if the library is missing, loading
+fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libanomps.so")
+
+MPS_OK = 0
+PREC_FP64, PREC_FP32, PREC_SPLIT_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16}
+IMG_NONFINITE, IMG_NO_CONVERGENCE = 1, 2
+MAX_BOND = 16
+
+_lib = None
+
+
+class MpsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"anomps error {code}: {msg}")
+        self.code = code
+
+
+class MpsBatch(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32),
+        ("chi", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("layers_done", ctypes.c_int32),
+        ("state", ctypes.c_void_p),
+        ("env", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = {
+    "mps_bond_dim": (ctypes.c_int32, [ctypes.c_int32] * 4),
+    "mps_slot_dim": (ctypes.c_int32, [ctypes.c_int32] * 3),
+    "mps_state_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 5),
+    "mps_env_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 5),
+    "mps_init_batch": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_apply_layer": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_validate_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "mps_pauli_pair_expect": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_ano_coeffs": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p,
+                                                             ctypes.c_int32, ctypes.c_void_p]),
+    "mps_ano_readout": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 3 +
+                        [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mps_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libanomps.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build it with "
+                               "`python -m paper_2607_10280_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(rc: int):
+    if rc != MPS_OK:
+        raise MpsError(rc, lib().mps_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def bond_dim(n, chi, layers, bond) -> int:
+    return int(lib().mps_bond_dim(n, chi, layers, bond))
+
+
+def slot_dim(n, chi, layers) -> int:
+    return int(lib().mps_slot_dim(n, chi, layers))
+
+
+def state_bytes(n, chi, layers, batch, precision) -> int:
+    return int(lib().mps_state_bytes(n, chi, layers, batch, precision))
+
+
+def env_bytes(n, chi, layers, batch, precision) -> int:
+    return int(lib().mps_env_bytes(n, chi, layers, batch, precision))
+
+
+def validate_pairs(pairs: np.ndarray, n_sites: int) -> None:
+    p = np.ascontiguousarray(pairs, dtype=np.int32)
+    _check(lib().mps_validate_pairs(p.ctypes.data_as(ctypes.c_void_p), len(p), n_sites))
+
+
+def footprint_bytes(n, chi, layers, batch, precision, m) -> int:
+    """HBM bytes one batch holds: state + environments + status + Pauli outputs."""
+    real = 8 if precision == PREC_FP64 else 4
+    return (state_bytes(n, chi, layers, batch, precision) +
+            env_bytes(n, chi, layers, batch, precision) + 4 * batch + batch * m * 15 * real)
+
+
+@dataclass
+class Batch:
+    """A device-resident batch: the descriptor plus the torch tensors that own its memory."""
+    desc: MpsBatch
+    state: object
+    env: object
+    status: object
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.desc.precision == PREC_FP64 else torch.float32
+
+
+def new_batch(n_sites: int, chi: int, n_layers: int, batch: int, precision: int = PREC_FP32,
+              device="cuda") -> Batch:
+    import torch
+    sb = state_bytes(n_sites, chi, n_layers, batch, precision)
+    eb = env_bytes(n_sites, chi, n_layers, batch, precision)
+    if sb == 0 or eb == 0:
+        raise MpsError(-1, lib().mps_last_error().decode())
+    state = torch.empty(sb, dtype=torch.uint8, device=device)
+    env = torch.empty(eb, dtype=torch.uint8, device=device)
+    status = torch.zeros(batch, dtype=torch.int32, device=device)
+    desc = MpsBatch(n_sites, chi, n_layers, batch, precision, 0,
+                    state.data_ptr(), env.data_ptr(), status.data_ptr())
+    return Batch(desc, state, env, status)
+
+
+def init_batch(b: Batch, pixels, stream=None) -> None:
+    assert pixels.dtype.is_floating_point and pixels.is_cuda and pixels.is_contiguous()
+    assert pixels.numel() == b.desc.batch * b.desc.n_sites
+    _check(lib().mps_init_batch(ctypes.byref(b.desc), _ptr(pixels), _stream(stream)))
+
+
+def apply_layer(b: Batch, theta, phi, trunc_err=None, stream=None) -> None:
+    for t in (theta, phi):
+        assert t.is_cuda and t.is_contiguous() and t.numel() == b.desc.n_sites
+    _check(lib().mps_apply_layer(ctypes.byref(b.desc), _ptr(theta), _ptr(phi), _ptr(trunc_err),
+                                 _stream(stream)))
+
+
+def pauli_pair_expect(b: Batch, pairs_dev, out, stream=None) -> None:
+    m = 0 if pairs_dev is None else pairs_dev.shape[0]
+    _check(lib().mps_pauli_pair_expect(ctypes.byref(b.desc), _ptr(pairs_dev), m, _ptr(out),
+                                       _stream(stream)))
+
+
+def ano_coeffs(A, B, D, coeff, stream=None) -> None:
+    is_f64 = int(coeff.dtype.itemsize == 8)
+    _check(lib().mps_ano_coeffs(_ptr(A), _ptr(B), _ptr(D), A.shape[0], _ptr(coeff), is_f64,
+                                _stream(stream)))
+
+
+def ano_readout(pauli, coeff, W, bias, y, stream=None) -> None:
+    batch, m = pauli.shape[0], pauli.shape[1]
+    out_dim = W.shape[0]
+    is_f64 = int(y.dtype.itemsize == 8)
+    _check(lib().mps_ano_readout(_ptr(pauli), _ptr(coeff), _ptr(W), _ptr(bias), batch, m,
+                                 out_dim, _ptr(y), is_f64, _stream(stream)))
+
+
+def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_FP32,
+                     stream=None, return_trunc_err: bool = False):
+    """Whole path for one batch: encode, all layers, Pauli-pair expectations.
+
+    pixels [B][n] (host numpy or device tensor), theta/phi [L][n], pairs [m][2] (numpy, validated
+    on the host).  Returns device tensors (features [B][m][15], status [B][, trunc_err [B][L][n-1]]).
+    """
+    import torch
+    dev = torch.device("cuda")
+    pairs_np = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    pix = torch.as_tensor(pixels, dtype=torch.float64, device=dev).contiguous()
+    B, n = pix.shape
+    validate_pairs(pairs_np, n)
+    th = torch.as_tensor(np.asarray(theta), dtype=torch.float64, device=dev).contiguous()
+    ph = torch.as_tensor(np.asarray(phi), dtype=torch.float64, device=dev).contiguous()
+    L = th.shape[0]
+    b = new_batch(n, chi, L, B, precision)
+    init_batch(b, pix, stream)
+    te = torch.zeros((B, max(L, 1), n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+    for layer in range(L):
+        tl = torch.empty((B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+        apply_layer(b, th[layer], ph[layer], tl, stream)
+        if return_trunc_err:
+            te[:, layer] = tl
+    pd = torch.as_tensor(pairs_np, device=dev)
+    out = torch.empty((B, len(pairs_np), 15), dtype=b.real_dtype, device=dev)
+    pauli_pair_expect(b, pd, out, stream)
+    if return_trunc_err:
+        return out, b.status, te
+    return out, b.status

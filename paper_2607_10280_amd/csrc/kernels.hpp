@@ -1,0 +1,34 @@
+// Host-side launchers of the anomps kernels (internal; the public interface is anomps.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace anomps {
+
+template <typename T>
+hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch, int* status,
+                         hipStream_t stream);
+
+template <typename T>
+hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch,
+                        const double* theta, const double* phi, double* trunc_err, int* status,
+                        hipStream_t stream);
+
+// Environment sweeps (left and right) and pair expectations.  T = storage type of the state,
+// C = compute/output type of the measurement (double for FP64 batches, float otherwise).
+template <typename T, typename C>
+hipError_t launch_envs(const T* state, C* env, int n, int chi, int S, int layers, int batch,
+                       hipStream_t stream);
+
+template <typename T, typename C>
+hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, int n, int chi,
+                        int S, int layers, int batch, C* out, hipStream_t stream);
+
+template <typename R>
+hipError_t launch_coeffs(const R* A, const R* B, const R* D, int m, R* coeff, hipStream_t stream);
+
+template <typename R>
+hipError_t launch_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int batch,
+                          int m, int out_dim, R* y, hipStream_t stream);
+
+}  // namespace anomps

@@ -1,0 +1,88 @@
+// Adaptive-observable readout: Pauli-basis coefficients of H_q (Eq. (4)), features by linearity
+// (Eq. (5)) and the linear reconstruction y = W q + b (Eq. (6)).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace anomps {
+
+template <typename R>
+__device__ __forceinline__ cx<R> pauli_e(int a, int r, int c) {
+  switch (a) {
+    case 0: return cx<R>{(R)(r == c), (R)0};
+    case 1: return cx<R>{(R)(r != c), (R)0};
+    case 2: return (r == c) ? cx<R>{(R)0, (R)0} : cx<R>{(R)0, (R)(r == 0 ? -1 : 1)};
+    default: return (r == c) ? cx<R>{(R)(r == 0 ? 1 : -1), (R)0} : cx<R>{(R)0, (R)0};
+  }
+}
+
+// One thread per (observable, alpha): coeff[q][alpha] = Re Tr(H_q (P_a (x) P_c)) / 4.
+template <typename R>
+__global__ void k_coeffs(const R* A, const R* B, const R* D, int m, R* coeff) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= m * 16) return;
+  const int q = gid / 16, al = gid % 16, pa = al >> 2, pc = al & 3;
+  // H[j][k]: diagonal D, upper (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) = A + iB, lower = conj.
+  auto h = [&](int j, int k) -> cx<R> {
+    if (j == k) return cx<R>{D[q * 4 + j], (R)0};
+    const int lo = j < k ? j : k, hi = j < k ? k : j;
+    const int idx = lo == 0 ? hi - 1 : (lo == 1 ? hi + 1 : 5);
+    const R im = B[q * 6 + idx];
+    return cx<R>{A[q * 6 + idx], j < k ? im : -im};
+  };
+  R acc = (R)0;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      // (P_a (x) P_c)[c][r] with row/col index s_i*2 + s_j
+      const cx<R> p = cmul(pauli_e<R>(pa, c >> 1, r >> 1), pauli_e<R>(pc, c & 1, r & 1));
+      const cx<R> hv = h(r, c);
+      acc += hv.re * p.re - hv.im * p.im;
+    }
+  coeff[gid] = (R)0.25 * acc;
+}
+
+// One workgroup per image: q[j] in LDS, then y[o] = sum_j W[o][j] q[j] + bias[o].
+template <typename R>
+__global__ void k_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int m,
+                          int out_dim, R* y) {
+  extern __shared__ unsigned char smem[];
+  R* qv = reinterpret_cast<R*>(smem);
+  const int b = blockIdx.x;
+  const R* pb = pauli + (size_t)b * m * 15;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    R acc = coeff[j * 16];
+    for (int al = 0; al < 15; ++al) acc += coeff[j * 16 + al + 1] * pb[j * 15 + al];
+    qv[j] = acc;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < out_dim; o += blockDim.x) {
+    R acc = bias ? bias[o] : (R)0;
+    const R* wr = W + (size_t)o * m;
+    for (int j = 0; j < m; ++j) acc += wr[j] * qv[j];
+    y[(size_t)b * out_dim + o] = acc;
+  }
+}
+
+template <typename R>
+hipError_t launch_coeffs(const R* A, const R* B, const R* D, int m, R* coeff, hipStream_t stream) {
+  if (m == 0) return hipSuccess;
+  const int threads = 256;
+  hipLaunchKernelGGL(k_coeffs<R>, dim3((m * 16 + threads - 1) / threads), dim3(threads), 0, stream,
+                     A, B, D, m, coeff);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int batch,
+                          int m, int out_dim, R* y, hipStream_t stream) {
+  if (batch == 0 || out_dim == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_readout<R>, dim3(batch), dim3(256), (size_t)m * sizeof(R), stream, pauli,
+                     coeff, W, bias, m, out_dim, y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_coeffs<double>(const double*, const double*, const double*, int, double*, hipStream_t);
+template hipError_t launch_coeffs<float>(const float*, const float*, const float*, int, float*, hipStream_t);
+template hipError_t launch_readout<double>(const double*, const double*, const double*, const double*, int, int, int, double*, hipStream_t);
+template hipError_t launch_readout<float>(const float*, const float*, const float*, const float*, int, int, int, float*, hipStream_t);
+
+}  // namespace anomps

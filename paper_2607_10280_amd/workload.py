@@ -1,0 +1,86 @@
+"""Algorithmic work model of the feature-extraction path (flops and HBM bytes per image).
+
+These are the counts a roofline is priced with: the operations the method needs at the bond
+dimensions it actually uses, not what a particular kernel executes.
+
+* A complex multiply-add (cMAC) is 8 real flops.
+* SVD of an m x n complex matrix (m >= n; singular values, thin U and V) is priced with the
+  R-SVD count of Golub & Van Loan (6 m n^2 + 20 n^3 real flops) times 4 for complex
+  arithmetic; a one-sided Jacobi SVD typically executes 1.5-3x this many flops.
+* Bond dimensions follow the rule D_k = min(chi, 2^layers, 2^(k+1), 2^(n-k-1)).
+"""
+from __future__ import annotations
+
+CMAC = 8
+
+
+def bond(n: int, chi: int, layers: int, k: int) -> int:
+    if k < 0 or k >= n - 1:
+        return 1
+    return min(chi, 2 ** layers, 2 ** (k + 1), 2 ** (n - k - 1))
+
+
+def svd_flops(m: int, n: int) -> float:
+    if m < n:
+        m, n = n, m
+    return 4.0 * (6.0 * m * n * n + 20.0 * n ** 3)
+
+
+def layer_flops(n: int, chi: int, layer: int) -> dict:
+    """Work of applying layer `layer` (0-based) to one image: canonical sweep (gate + SVD of
+    each site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left neighbour), then the
+    ladder (two-site contraction, SVD, U^H Theta' for the new centre)."""
+    d_old = lambda k: bond(n, chi, layer, k)
+    d_new = lambda k: bond(n, chi, layer + 1, k)
+    svd = other = 0.0
+    for k in range(n - 1, 0, -1):
+        dl, dr = d_old(k - 1), d_old(k)
+        svd += svd_flops(2 * dr, dl)
+        other += CMAC * (dl * dl * 2 * dr + 2 * d_old(k - 2) * dl * dl + 4 * dl * dr)
+    other += CMAC * 4 * d_old(0)
+    for k in range(n - 1):
+        dl, dc, dr, d = d_new(k - 1), d_old(k), d_old(k + 1), d_new(k)
+        svd += svd_flops(2 * dl, 2 * dr)
+        other += CMAC * (2 * dl * dc * 2 * dr + 2 * d * dl * dc + d * 2 * dr * 2 * dc)
+    return {"svd_fp64": svd, "other_fp64": other, "total_fp64": svd + other}
+
+
+def env_flops(n: int, chi: int, layers: int) -> float:
+    d = lambda k: bond(n, chi, layers, k)
+    total = 0
+    for k in range(n):
+        dl, dr = d(k - 1), d(k)
+        total += 2 * dl * dr * dl + dr * dr * 2 * dl   # left sweep
+        total += 2 * dr * dl * dr + dl * dl * 2 * dr   # right sweep
+    return CMAC * float(total)
+
+
+def pair_flops(n: int, chi: int, layers: int, pairs) -> float:
+    """Open at i, carry through i+1..j-1 (shared by all partners of i), close at each j."""
+    d = lambda k: bond(n, chi, layers, k)
+    by_start: dict = {}
+    for i, j in pairs:
+        by_start.setdefault(int(i), []).append(int(j))
+    total = 0
+    for i, js in by_start.items():
+        dl, dc = d(i - 1), d(i)
+        total += 2 * dl * dc * dl + 3 * dc * dc * dl
+        for k in range(i + 1, max(js)):
+            a, b = d(k - 1), d(k)
+            total += 6 * a * b * a + 3 * b * b * 2 * a
+        for j in js:
+            dd, dj = d(j - 1), d(j)
+            total += 2 * dj * dd * dj + 3 * dd * dd * dj + 16 * dd * dd
+    return CMAC * float(total)
+
+
+def state_bytes(n: int, chi: int, layers: int, real_bytes: int) -> int:
+    """Bytes of one image's site tensors at the given number of layers (used corners only)."""
+    return sum(bond(n, chi, layers, k - 1) * 2 * bond(n, chi, layers, k) * 2 * real_bytes
+               for k in range(n))
+
+
+def layer_bytes(n: int, chi: int, layer: int, real_bytes: int) -> int:
+    """HBM traffic of one layer for one image: the canonical sweep reads and writes every
+    tensor once, the ladder reads and writes every tensor once."""
+    return 2 * state_bytes(n, chi, layer, real_bytes) + 2 * state_bytes(n, chi, layer + 1, real_bytes)

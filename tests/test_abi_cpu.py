@@ -1,0 +1,78 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-only calls (sizes, bond-dimension rule, pair validation) behave as documented.  No
+kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mps as omps
+from paper_2607_10280_amd import anomps, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "anomps.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mps_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(anomps.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(anomps.EXPORTS)
+
+
+def test_bond_dim_rule_matches_oracle():
+    x = inputs.uniform_pixels(1, 12, 3)[0]
+    th, ph = inputs.layer_angles(4, 12, 4)
+    for chi in (1, 2, 3, 4, 8, 16):
+        m = omps.product_mps(x)
+        for layer in range(4):
+            omps.apply_layer(m, th[layer], ph[layer], chi)
+            got = [anomps.bond_dim(12, chi, layer + 1, k) for k in range(11)]
+            assert got == m.bond_dims(), (chi, layer)
+    assert anomps.bond_dim(49, 16, 4, -1) == 1 and anomps.bond_dim(49, 16, 4, 48) == 1
+    assert anomps.bond_dim(49, 16, 4, 49) == 0
+
+
+def test_sizes():
+    P = anomps.PREC_FP32
+    assert anomps.slot_dim(49, 16, 4) == 16
+    assert anomps.slot_dim(49, 16, 0) == 2
+    assert anomps.slot_dim(256, 64, 2) == 4
+    assert anomps.state_bytes(49, 16, 4, 1024, P) == 1024 * 49 * 2 * 16 * 16 * 2 * 4
+    assert anomps.env_bytes(49, 16, 4, 1024, P) == 1024 * 2 * 50 * 16 * 16 * 2 * 4
+    assert anomps.state_bytes(49, 16, 4, 2, anomps.PREC_FP64) == 2 * 49 * 2 * 256 * 2 * 8
+    # over capacity: bond 32 is beyond this build
+    assert anomps.state_bytes(49, 32, 5, 1, P) == 0
+    assert "MPS_MAX_BOND" in anomps.lib().mps_last_error().decode()
+    assert anomps.state_bytes(1, 4, 1, 1, P) == 0
+    assert anomps.state_bytes(16, 4, 1, 1, 7) == 0
+
+
+def test_validate_pairs():
+    anomps.validate_pairs(inputs.neighbour_pairs(7), 49)
+    anomps.validate_pairs(np.zeros((0, 2), np.int32), 49)
+    for bad in ([(3, 3)], [(4, 2)], [(0, 49)], [(-1, 2)]):
+        with pytest.raises(anomps.MpsError) as e:
+            anomps.validate_pairs(np.array(bad, np.int32), 49)
+        assert e.value.code == -1
+    many = np.array([(0, j) for j in range(1, 300)], np.int32)
+    with pytest.raises(anomps.MpsError) as e:
+        anomps.validate_pairs(many, 400)
+    assert e.value.code == -2
+
+
+def test_neighbour_pairs_layout():
+    p = inputs.neighbour_pairs(7)
+    assert p.shape == (84, 2)
+    assert tuple(p[0]) == (0, 1) and tuple(p[41]) == (47, 48) and tuple(p[42]) == (0, 7)
+    assert np.all(p[:42, 1] - p[:42, 0] == 1) and np.all(p[42:, 1] - p[42:, 0] == 7)
+    assert inputs.neighbour_pairs(16).shape == (480, 2)
