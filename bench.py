@@ -47,8 +47,12 @@ def parse():
 
 
 # ----------------------------------------------------------------------------- CPU baseline
+def _single_thread():
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+
+
 def _oracle_worker(args):
-    os.environ["OMP_NUM_THREADS"] = "1"
     x, th, ph, pairs, chi = args
     from oracle import features as ofeat
     t0 = time.perf_counter()
@@ -62,7 +66,7 @@ def cpu_baseline(x, th, ph, pairs, chi, sample):
     jobs = [(x[i], th, ph, pairs, chi) for i in range(sample)]
     t0 = time.perf_counter()
     ctx = mp.get_context("spawn")
-    with ctx.Pool(cores, initializer=os.environ.__setitem__, initargs=("OMP_NUM_THREADS", "1")) as pool:
+    with ctx.Pool(cores, initializer=_single_thread) as pool:
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
     feats = np.stack([r[0] for r in res])
