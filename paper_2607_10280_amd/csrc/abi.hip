@@ -161,6 +161,9 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
     e = launch_envs<double, double>((const double*)b->state, (double*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)
       e = launch_pairs<double, double>((const double*)b->state, (const double*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
+  } else if (S == 16) {
+    e = launch_measure16((const float*)b->state, (float*)b->env, pairs, m, b->n_sites, b->chi, L,
+                         b->batch, (float*)out, stream);
   } else {
     e = launch_envs<float, float>((const float*)b->state, (float*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)

@@ -24,6 +24,10 @@ template <typename T, typename C>
 hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, int n, int chi,
                         int S, int layers, int batch, C* out, hipStream_t stream);
 
+// Matrix-core measurement for 16-wide slots in FP32 (environments + pairs).
+hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
+                            int chi, int layers, int batch, float* out, hipStream_t stream);
+
 template <typename R>
 hipError_t launch_coeffs(const R* A, const R* B, const R* D, int m, R* coeff, hipStream_t stream);
 

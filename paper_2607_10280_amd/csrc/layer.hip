@@ -40,94 +40,152 @@ __global__ void k_encode(T* state, const double* pixels, int n, int S, int* stat
 }
 
 // ------------------------------------------------------------------------------- layer
-template <int S>
+// LDS of one image.  `mat` holds the matrix being factorised column-major with leading
+// dimension LD (>= 16 so that a team of 16 lanes can always address padded rows); the
+// neighbour tensor `tb` keeps the storage type (it arrives from HBM in that type).
+template <int S, typename T>
 struct LayerShared {
-  cd mat[(2 * S) * (2 * S)];  // column-major working matrix, leading dimension 2S
+  static constexpr int LD = (2 * S > 16) ? 2 * S : 16;
+  cd mat[LD * 2 * S];
   cd ta[2 * S * S];           // centre tensor [a][s][c] at (a*2+s)*S + c
-  cd tb[2 * S * S];           // neighbour tensor [c][t][b] at (c*2+t)*S + b
+  cx<T> tb[2 * S * S];        // neighbour tensor [c][t][b] at (c*2+t)*S + b
   cd uq[2 * S * S];           // U [r][j] at r*S + j  (ladder) or V*Sigma [j][a] at j*S + a (sweep)
   double sig2[2 * S];
   int order[2 * S];
 };
 
-// One-sided (Hestenes) Jacobi on the N columns (length M) of `mat` in FP64.  Column pairs are
-// scheduled by the round-robin tournament (N-1 rounds of disjoint pairs per sweep); a team of
-// T lanes owns one pair per round and reduces its three inner products with lane shuffles.
-// A pair is rotated when |x^H y| > tol sqrt(|x|^2 |y|^2); columns whose squared norm is below
-// tiny2 = 1e-30 |A|_F^2 are treated as numerically zero.  On return sig2[c] = |w_c|^2.
-template <int S>
-__device__ int jacobi_columns(LayerShared<S>& sh, int M, int N, double* tiny2_out) {
-  constexpr int LD = 2 * S;
-  constexpr int RMAX = (2 * S * S + kLayerThreads - 1) / kLayerThreads > 0
-                           ? (2 * S * S + kLayerThreads - 1) / kLayerThreads
-                           : 1;
+// Cross-lane moves inside a 16-lane row (DPP): mirror, half-mirror, quad swaps.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned team of T lanes (T <= 16); every lane gets the bitwise-same result
+// (each step adds a lane's value to its mirror image, so all lanes add the same operands).
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+  if constexpr (T >= 16) v += dpp_d<0x140>(v);  // row_mirror
+  if constexpr (T >= 8) v += dpp_d<0x141>(v);   // row_half_mirror
+  if constexpr (T >= 4) v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (T >= 2) v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  return v;
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps (full FP64 precision).
+__device__ __forceinline__ double rsqrt_full(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+// 1/x for x >= 1 to ~2^-46 (used only for the rotation angle, which need not be exact).
+__device__ __forceinline__ double rcp_fast(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__host__ __device__ inline int pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Tile shape of the Jacobi sweep for an M x N matrix: NP = padded column count (power of 2),
+// NP/2 column pairs per round, T lanes per pair (<= 16), R rows per lane, MP = R*T rows.
+struct JShape {
+  int NP, T, R, MP;
+};
+__host__ __device__ inline JShape jacobi_shape(int M, int N) {
+  JShape j;
+  j.NP = pow2ceil(N < 2 ? 2 : N);
+  const int P = j.NP / 2;
+  j.T = (64 / P) < 16 ? 64 / P : 16;
+  j.R = pow2ceil((M + j.T - 1) / j.T);
+  j.MP = j.R * j.T;
+  return j;
+}
+
+// One-sided (Hestenes) Jacobi on the N columns of `mat` (rows [M, MP) must be zero) in FP64.
+// Column pairs follow the round-robin tournament: NP-1 rounds of NP/2 disjoint pairs per
+// sweep.  A team of T lanes owns a pair; each lane holds R rows of both columns in registers,
+// the team reduces |x|^2, |y|^2 and x^H y with DPP row moves, and every lane of the team
+// evaluates the same rotation.  A pair is rotated when |x^H y|^2 > tol^2 |x|^2 |y|^2 with
+// tol = M eps; columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2 count as numerically zero.
+// On return sig2[c] = |w_c|^2 for c < N.  Returns kImgNoConvergence if the sweep limit hit.
+template <int S, typename T, int NP, int R>
+__device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N, double* tiny2_out) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int P = NP / 2;
+  constexpr int TM = (64 / P) < 16 ? 64 / P : 16;
+  constexpr int MP = R * TM;
+  static_assert(MP <= LD, "tile rows exceed the LDS column");
   const int tid = threadIdx.x;
+  const int q = tid / TM, lt = tid % TM;
+  const bool active = q < P;
   double f = 0.0;
-  for (int idx = tid; idx < M * N; idx += kLayerThreads) {
-    const cd v = sh.mat[(idx / M) * LD + (idx % M)];
-    f += v.re * v.re + v.im * v.im;
+  for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
+    const cd v = sh.mat[(idx / MP) * LD + (idx % MP)];
+    f = fma(v.re, v.re, fma(v.im, v.im, f));
   }
   f = wave_sum(f);
   const double tiny2 = 1e-30 * f;
   *tiny2_out = tiny2;
   const double tol = (double)M * 2.220446049250313e-16;
-  const int Nr = N + (N & 1);
-  const int P = Nr / 2;
-  int T = 64;
-  while (T * P > kLayerThreads) T >>= 1;
-  const int q = tid / T;
-  const int lt = tid % T;
-  const bool active = q < P;
-  int sweep = 0;
+  const double tol2 = tol * tol;
   bool converged = (N < 2);
+  int sweep = 0;
   for (; !converged && sweep < kMaxSweeps; ++sweep) {
     int rotated = 0;
-    for (int r = 0; r < Nr - 1; ++r) {
+    for (int r = 0; r < NP - 1; ++r) {
       int ci = 0, cj = 0;
       if (active) {
-        ci = (q == 0) ? 0 : 1 + (q - 1 + r) % (Nr - 1);
-        const int p2 = Nr - 1 - q;
-        cj = 1 + (p2 - 1 + r) % (Nr - 1);
+        if (q > 0) {
+          int v = q - 1 + r;
+          if (v >= NP - 1) v -= NP - 1;
+          ci = 1 + v;
+        }
+        int v = NP - 2 - q + r;
+        if (v >= NP - 1) v -= NP - 1;
+        cj = 1 + v;
       }
       const bool valid = active && ci < N && cj < N;
-      cd x[RMAX], y[RMAX];
+      cd x[R], y[R];
       double a = 0.0, bb = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
-      for (int t = 0; t < RMAX; ++t) {
-        const int rr = lt + t * T;
-        if (valid && rr < M) {
-          x[t] = sh.mat[ci * LD + rr];
-          y[t] = sh.mat[cj * LD + rr];
-          a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
-          bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
-          gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
-          gi = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, gi));
-        }
+      for (int t = 0; t < R; ++t) {
+        const int rr = lt + t * TM;
+        x[t] = sh.mat[ci * LD + rr];
+        y[t] = sh.mat[cj * LD + rr];
+        a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
+        bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
+        gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
+        gi = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, gi));
       }
-      for (int off = T >> 1; off >= 1; off >>= 1) {
-        a += __shfl_xor(a, off);
-        bb += __shfl_xor(bb, off);
-        gr += __shfl_xor(gr, off);
-        gi += __shfl_xor(gi, off);
-      }
-      if (valid) {
-        const double ag = hypot(gr, gi);
-        if (a > tiny2 && bb > tiny2 && ag > tol * sqrt(a * bb)) {
-          rotated = 1;
-          const double zeta = (bb - a) / (2.0 * ag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double s = c * t;
-          const cd e{gr / ag, -gi / ag};  // conj(g)/|g|
+      a = team_sum<TM>(a);
+      bb = team_sum<TM>(bb);
+      gr = team_sum<TM>(gr);
+      gi = team_sum<TM>(gi);
+      const double ag2 = fma(gr, gr, gi * gi);
+      if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * a * bb) {
+        rotated = 1;
+        const double rg = rsqrt_full(ag2);                 // 1/|g|
+        const double zeta = (bb - a) * 0.5 * rg;
+        const double w = fma(zeta, zeta, 1.0);
+        double rw = __builtin_amdgcn_rsq(w);
+        rw = rw * fma(-0.5 * w * rw, rw, 1.5);
+        const double t = copysign(rcp_fast(fabs(zeta) + w * rw), zeta);
+        const double c = rsqrt_full(fma(t, t, 1.0));
+        const double s = c * t;
+        const cd e{gr * rg, -gi * rg};                     // conj(g)/|g|
 #pragma unroll
-          for (int tt = 0; tt < RMAX; ++tt) {
-            const int rr = lt + tt * T;
-            if (rr < M) {
-              const cd ye = cmul(e, y[tt]);
-              sh.mat[ci * LD + rr] = cd{c * x[tt].re - s * ye.re, c * x[tt].im - s * ye.im};
-              sh.mat[cj * LD + rr] = cd{s * x[tt].re + c * ye.re, s * x[tt].im + c * ye.im};
-            }
-          }
+        for (int tt = 0; tt < R; ++tt) {
+          const int rr = lt + tt * TM;
+          const cd ye = cmul(e, y[tt]);
+          sh.mat[ci * LD + rr] = cd{fma(c, x[tt].re, -s * ye.re), fma(c, x[tt].im, -s * ye.im)};
+          sh.mat[cj * LD + rr] = cd{fma(s, x[tt].re, c * ye.re), fma(s, x[tt].im, c * ye.im)};
         }
       }
       __syncthreads();
@@ -136,8 +194,8 @@ __device__ int jacobi_columns(LayerShared<S>& sh, int M, int N, double* tiny2_ou
   }
   for (int col = tid; col < N; col += kLayerThreads) {
     double s2 = 0.0;
-    for (int r = 0; r < M; ++r) {
-      const cd v = sh.mat[col * LD + r];
+    for (int rr = 0; rr < MP; ++rr) {
+      const cd v = sh.mat[col * LD + rr];
       s2 = fma(v.re, v.re, fma(v.im, v.im, s2));
     }
     sh.sig2[col] = s2;
@@ -146,9 +204,25 @@ __device__ int jacobi_columns(LayerShared<S>& sh, int M, int N, double* tiny2_ou
   return converged ? 0 : kImgNoConvergence;
 }
 
+template <int S, typename T>
+__device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N, double* tiny2) {
+  const JShape js = jacobi_shape(M, N);
+#define ANOMPS_JT(NPV, RV)                                                           \
+  if (js.NP == NPV && js.R == RV) {                                                  \
+    if constexpr (NPV <= 2 * S && RV * ((64 / (NPV / 2)) < 16 ? 64 / (NPV / 2) : 16) <= \
+                                       LayerShared<S, T>::LD)                        \
+      return jacobi_tile<S, T, NPV, RV>(sh, M, N, tiny2);                            \
+  }
+#define ANOMPS_JN(NPV) ANOMPS_JT(NPV, 1) ANOMPS_JT(NPV, 2) ANOMPS_JT(NPV, 4) ANOMPS_JT(NPV, 8)
+  ANOMPS_JN(2) ANOMPS_JN(4) ANOMPS_JN(8) ANOMPS_JN(16) ANOMPS_JN(32)
+#undef ANOMPS_JN
+#undef ANOMPS_JT
+  return kImgNoConvergence;  // unreachable for shapes within the slot
+}
+
 // Apply U = R_Y(theta) R_Z(phi) to the physical index of the (Dl x 2 x Dr) tensor in ta.
-template <int S>
-__device__ void apply_gate(LayerShared<S>& sh, int Dl, int Dr, double theta, double phi) {
+template <int S, typename T>
+__device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, double theta, double phi) {
   double st, ct, sp, cp;
   sincos(0.5 * theta, &st, &ct);
   sincos(0.5 * phi, &sp, &cp);
@@ -168,13 +242,33 @@ __device__ void apply_gate(LayerShared<S>& sh, int Dl, int Dr, double theta, dou
   __syncthreads();
 }
 
+// Register prefetch of one site tensor (Dl x 2 x Dr, storage type) so that its HBM/L2
+// latency overlaps the factorisation of the current bond.
 template <int S, typename T>
-__device__ void load_tensor(cd* dst, const T* slot, int Dl, int Dr) {
-  for (int idx = threadIdx.x; idx < Dl * 2 * Dr; idx += kLayerThreads) {
-    const int row = idx / Dr, b = idx % Dr;  // row = a*2 + s
-    dst[row * S + b] = load_c<T, double>(slot, (size_t)row * S + b);
+struct SitePrefetch {
+  static constexpr int PF = (2 * S * S + kLayerThreads - 1) / kLayerThreads;
+  cx<T> v[PF];
+  int Dl = 0, Dr = 0;
+  __device__ void load(const T* slot, int dl, int dr) {
+    Dl = dl;
+    Dr = dr;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int idx = threadIdx.x + i * kLayerThreads;
+      if (idx < Dl * 2 * Dr) {
+        const int row = idx / Dr, b = idx % Dr;
+        v[i] = cx<T>{slot[2 * ((size_t)row * S + b)], slot[2 * ((size_t)row * S + b) + 1]};
+      }
+    }
   }
-}
+  __device__ void commit(cx<T>* dst) const {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int idx = threadIdx.x + i * kLayerThreads;
+      if (idx < Dl * 2 * Dr) dst[(idx / Dr) * S + idx % Dr] = v[i];
+    }
+  }
+};
 
 template <int S, typename T>
 __device__ void store_tensor(T* slot, const cd* src, int Dl, int Dr) {
@@ -184,34 +278,46 @@ __device__ void store_tensor(T* slot, const cd* src, int Dl, int Dr) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ cd to_cd(cx<T> v) {
+  return cd{(double)v.re, (double)v.im};
+}
+
 // Applies layer `layer` (0-based) to one image whose n slots start at `st`.
 template <int S, typename T>
-__device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer,
+__device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
                             const double* theta, const double* phi, double* trunc_err,
                             int* status) {
-  constexpr int LD = 2 * S;
+  constexpr int LD = LayerShared<S, T>::LD;
   constexpr size_t SLOT = (size_t)2 * S * S * 2;  // T values per site slot
   const int tid = threadIdx.x;
   int flags = 0;
   auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
   auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
+  SitePrefetch<S, T> pf;
 
   // ---- right-to-left sweep: gate every site, make sites n-1..1 right-canonical.
-  load_tensor<S, T>(sh.ta, st + (size_t)(n - 1) * SLOT, dold(n - 2), 1);
+  pf.load(st + (size_t)(n - 1) * SLOT, dold(n - 2), 1);
+  pf.commit(sh.tb);
+  __syncthreads();
+  for (int idx = tid; idx < dold(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * S] = to_cd(sh.tb[idx * S]);
   __syncthreads();
   for (int k = n - 1; k >= 1; --k) {
-    const int Dl = dold(k - 1), Dr = dold(k);
-    apply_gate<S>(sh, Dl, Dr, theta[k], phi[k]);
-    // mat = t^H: rows (s, b) -> s*Dr + b, columns a.
+    const int Dl = dold(k - 1), Dr = dold(k), Dll = dold(k - 2);
+    pf.load(st + (size_t)(k - 1) * SLOT, Dll, Dl);
+    apply_gate<S, T>(sh, Dl, Dr, theta[k], phi[k]);
+    // mat = t^H: rows (s, b) -> s*Dr + b, columns a; rows [M, MP) zero.
     const int M = 2 * Dr, N = Dl;
-    for (int idx = tid; idx < N * M; idx += kLayerThreads) {
-      const int a = idx / M, rr = idx % M;
-      const int s = rr / Dr, b = rr % Dr;
-      sh.mat[a * LD + rr] = cconj(sh.ta[(a * 2 + s) * S + b]);
+    const int MP = jacobi_shape(M, N).MP;
+    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
+      const int a = idx / MP, rr = idx % MP;
+      cd v{0.0, 0.0};
+      if (rr < M) v = cconj(sh.ta[(a * 2 + rr / Dr) * S + rr % Dr]);
+      sh.mat[a * LD + rr] = v;
     }
     __syncthreads();
     double tiny2;
-    flags |= jacobi_columns<S>(sh, M, N, &tiny2);
+    flags |= jacobi_columns<S, T>(sh, M, N, &tiny2);
     // Right-canonical rows q_a^H and V*Sigma = t Q.
     T* slot = st + (size_t)k * SLOT;
     for (int idx = tid; idx < N * M; idx += kLayerThreads) {
@@ -219,7 +325,7 @@ __device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer
       const int s = rr / Dr, b = rr % Dr;
       const double s2 = sh.sig2[a];
       cd v{0.0, 0.0};
-      if (s2 > tiny2) v = cscale(cconj(sh.mat[a * LD + rr]), 1.0 / sqrt(s2));
+      if (s2 > tiny2) v = cscale(cconj(sh.mat[a * LD + rr]), rsqrt_full(s2));
       store_c<T, double>(slot, (size_t)(a * 2 + s) * S + b, v);
     }
     for (int idx = tid; idx < N * N; idx += kLayerThreads) {
@@ -227,44 +333,45 @@ __device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer
       const double s2 = sh.sig2[a];
       cd acc{0.0, 0.0};
       if (s2 > tiny2) {
-        for (int rr = 0; rr < M; ++rr) {
-          const int s = rr / Dr, b = rr % Dr;
-          cfma(acc, sh.ta[(j * 2 + s) * S + b], sh.mat[a * LD + rr]);
-        }
-        acc = cscale(acc, 1.0 / sqrt(s2));
+        for (int rr = 0; rr < M; ++rr)
+          cfma(acc, sh.ta[(j * 2 + rr / Dr) * S + rr % Dr], sh.mat[a * LD + rr]);
+        acc = cscale(acc, rsqrt_full(s2));
       }
       sh.uq[j * S + a] = acc;
     }
-    const int Dll = dold(k - 2);
-    load_tensor<S, T>(sh.tb, st + (size_t)(k - 1) * SLOT, Dll, Dl);
+    pf.commit(sh.tb);
     __syncthreads();
     for (int idx = tid; idx < Dll * 2 * Dl; idx += kLayerThreads) {
       const int row = idx / Dl, a = idx % Dl;
       cd acc{0.0, 0.0};
-      for (int j = 0; j < Dl; ++j) cfma(acc, sh.tb[row * S + j], sh.uq[j * S + a]);
+      for (int j = 0; j < Dl; ++j) cfma(acc, to_cd(sh.tb[row * S + j]), sh.uq[j * S + a]);
       sh.ta[row * S + a] = acc;
     }
     __syncthreads();
   }
-  apply_gate<S>(sh, 1, dold(0), theta[0], phi[0]);
+  apply_gate<S, T>(sh, 1, dold(0), theta[0], phi[0]);
 
   // ---- left-to-right CNOT ladder with SVD truncation.
+  pf.load(st + (size_t)1 * SLOT, dold(0), dold(1));
   for (int k = 0; k <= n - 2; ++k) {
     const int Dl = dnew(k - 1), Dc = dold(k), Dr = dold(k + 1);
-    load_tensor<S, T>(sh.tb, st + (size_t)(k + 1) * SLOT, Dc, Dr);
+    pf.commit(sh.tb);
     __syncthreads();
+    if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, dold(k + 1), dold(k + 2));
     const int M = 2 * Dl, N = 2 * Dr;
+    const int MP = jacobi_shape(M, N).MP;
     // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR s, b]   (CNOT control k)
-    for (int idx = tid; idx < M * N; idx += kLayerThreads) {
-      const int col = idx / M, row = idx % M;
+    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
+      const int col = idx / MP, row = idx % MP;
       const int t = col / Dr, b = col % Dr, s = row & 1;
       cd acc{0.0, 0.0};
-      for (int c = 0; c < Dc; ++c) cfma(acc, sh.ta[row * S + c], sh.tb[(c * 2 + (t ^ s)) * S + b]);
+      if (row < M)
+        for (int c = 0; c < Dc; ++c) cfma(acc, sh.ta[row * S + c], to_cd(sh.tb[(c * 2 + (t ^ s)) * S + b]));
       sh.mat[col * LD + row] = acc;
     }
     __syncthreads();
     double tiny2;
-    flags |= jacobi_columns<S>(sh, M, N, &tiny2);
+    flags |= jacobi_columns<S, T>(sh, M, N, &tiny2);
     const int D = min(chi, min(M, N));
     // Sort singular values (descending, ties by column index); NaN counts as zero.
     for (int c = tid; c < N; c += kLayerThreads) {
@@ -285,7 +392,7 @@ __device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer
       if (r < D) kept += v; else disc += v;
     }
     if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
-    const double inv_norm = (kept > 0.0) ? 1.0 / sqrt(kept) : 0.0;
+    const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
     if (tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
     // U columns = normalised kept columns of W (numerically zero columns become zero).
     for (int idx = tid; idx < M * D; idx += kLayerThreads) {
@@ -293,7 +400,7 @@ __device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer
       const int c = sh.order[j];
       const double s2 = sh.sig2[c];
       cd v{0.0, 0.0};
-      if (s2 > tiny2) v = cscale(sh.mat[c * LD + r], 1.0 / sqrt(s2));
+      if (s2 > tiny2) v = cscale(sh.mat[c * LD + r], rsqrt_full(s2));
       sh.uq[r * S + j] = v;
     }
     __syncthreads();
@@ -312,7 +419,7 @@ __device__ void layer_chain(LayerShared<S>& sh, T* st, int n, int chi, int layer
       cd acc{0.0, 0.0};
       for (int s = 0; s < 2; ++s)
         for (int c = 0; c < Dc; ++c)
-          cfma(acc, sh.mat[(s * S + j) * S + c], sh.tb[(c * 2 + (t ^ s)) * S + b]);
+          cfma(acc, sh.mat[(s * S + j) * S + c], to_cd(sh.tb[(c * 2 + (t ^ s)) * S + b]));
       sh.ta[(j * 2 + t) * S + b] = cscale(acc, inv_norm);
     }
     __syncthreads();
@@ -325,7 +432,7 @@ template <int S, typename T>
 __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int chi, int layer,
                                                          const double* theta, const double* phi,
                                                          double* trunc_err, int* status) {
-  __shared__ LayerShared<S> sh;
+  __shared__ LayerShared<S, T> sh;
   const int b = blockIdx.x;
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
   layer_chain<S, T>(sh, st, n, chi, layer, theta, phi,
