@@ -10,6 +10,8 @@
 
 namespace anomps {
 
+// One wavefront per image: every phase is latency-bound at these sizes, and splitting an image
+// over more waves costs more in barriers than the extra lanes save (measured at 128 and 256).
 constexpr int kLayerThreads = 64;
 constexpr int kMaxSweeps = 30;
 
@@ -45,14 +47,32 @@ __global__ void k_encode(T* state, const double* pixels, int n, int S, int* stat
 // neighbour tensor `tb` keeps the storage type (it arrives from HBM in that type).
 template <int S, typename T>
 struct LayerShared {
-  static constexpr int LD = (2 * S > 16) ? 2 * S : 16;
+  // Row strides are padded by one element so that lanes reading different rows of a tile do
+  // not fall on the same LDS banks (a power-of-two stride maps every row to bank 0).
+  static constexpr int LD = ((2 * S > 16) ? 2 * S : 16) + 1;
+  static constexpr int SP = S + 1;
   cd mat[LD * 2 * S];
-  cd ta[2 * S * S];           // centre tensor [a][s][c] at (a*2+s)*S + c
-  cx<T> tb[2 * S * S];        // neighbour tensor [c][t][b] at (c*2+t)*S + b
-  cd uq[2 * S * S];           // U [r][j] at r*S + j  (ladder) or V*Sigma [j][a] at j*S + a (sweep)
+  cd ta[2 * S * SP];          // centre tensor [a][s][c] at (a*2+s)*SP + c
+  cx<T> tb[2 * S * SP];       // neighbour tensor [c][t][b] at (c*2+t)*SP + b
+  cd uq[2 * S * SP];          // U [r][j] at r*SP + j (ladder) or V*Sigma [j][a] at j*SP + a (sweep)
   double sig2[2 * S];
-  int order[2 * S];
+  int rank[2 * S];            // columns in descending singular-value order
+  double red[kLayerThreads / 64];
+  double tiny2;               // negligible-column threshold of the last decomposition
 };
+
+// Sum over the workgroup (kLayerThreads lanes); every lane gets the same value.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if constexpr (kLayerThreads == 64) return v;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kLayerThreads / 64; ++w) t += red[w];
+  return t;
+}
 
 // Cross-lane moves inside a 16-lane row (DPP): mirror, half-mirror, quad swaps.
 template <int CTRL>
@@ -87,6 +107,16 @@ __device__ __forceinline__ double rcp_fast(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// Division by a runtime divisor that is usually a power of two (bond dimensions of the
+// CNOT-ladder circuit are): shifts on the fast path, integer division otherwise.
+struct FastDiv {
+  int d, sh;
+  bool p2;
+  __device__ explicit FastDiv(int d_) : d(d_), sh(__ffs(d_) - 1), p2((d_ & (d_ - 1)) == 0) {}
+  __device__ __forceinline__ int q(int x) const { return p2 ? (x >> sh) : x / d; }
+  __device__ __forceinline__ int r(int x) const { return p2 ? (x & (d - 1)) : x % d; }
+};
+
 __host__ __device__ inline int pow2ceil(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -102,7 +132,7 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
   JShape j;
   j.NP = pow2ceil(N < 2 ? 2 : N);
   const int P = j.NP / 2;
-  j.T = (64 / P) < 16 ? 64 / P : 16;
+  j.T = (kLayerThreads / P) < 16 ? kLayerThreads / P : 16;
   j.R = pow2ceil((M + j.T - 1) / j.T);
   j.MP = j.R * j.T;
   return j;
@@ -116,10 +146,10 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
 // tol = M eps; columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2 count as numerically zero.
 // On return sig2[c] = |w_c|^2 for c < N.  Returns kImgNoConvergence if the sweep limit hit.
 template <int S, typename T, int NP, int R>
-__device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N, double* tiny2_out) {
+__device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int P = NP / 2;
-  constexpr int TM = (64 / P) < 16 ? 64 / P : 16;
+  constexpr int TM = (kLayerThreads / P) < 16 ? kLayerThreads / P : 16;
   constexpr int MP = R * TM;
   static_assert(MP <= LD, "tile rows exceed the LDS column");
   const int tid = threadIdx.x;
@@ -130,47 +160,43 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N, double* tiny2_ou
     const cd v = sh.mat[(idx / MP) * LD + (idx % MP)];
     f = fma(v.re, v.re, fma(v.im, v.im, f));
   }
-  f = wave_sum(f);
+  f = block_sum(f, sh.red);
   const double tiny2 = 1e-30 * f;
-  *tiny2_out = tiny2;
+  if (tid == 0) sh.tiny2 = tiny2;
   const double tol = (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   bool converged = (N < 2);
   int sweep = 0;
   for (; !converged && sweep < kMaxSweeps; ++sweep) {
-    int rotated = 0;
+    int rotated = 0, big = 0;
+    // Round-robin positions: pair q = (pos(q), pos(NP-1-q)), pos(0) = 0 and pos(i) =
+    // 1 + ((i - 1 + r) mod (NP - 1)); advanced incrementally from round to round.
+    int ci = (q == 0) ? 0 : q, cj = NP - 1 - q;
     for (int r = 0; r < NP - 1; ++r) {
-      int ci = 0, cj = 0;
-      if (active) {
-        if (q > 0) {
-          int v = q - 1 + r;
-          if (v >= NP - 1) v -= NP - 1;
-          ci = 1 + v;
-        }
-        int v = NP - 2 - q + r;
-        if (v >= NP - 1) v -= NP - 1;
-        cj = 1 + v;
-      }
+      const int ci_ = active ? ci : 0, cj_ = active ? cj : 0;
       const bool valid = active && ci < N && cj < N;
       cd x[R], y[R];
-      double a = 0.0, bb = 0.0, gr = 0.0, gi = 0.0;
+      double gr = 0.0, gi = 0.0;
+      double a = 0.0, bb = 0.0;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int rr = lt + t * TM;
-        x[t] = sh.mat[ci * LD + rr];
-        y[t] = sh.mat[cj * LD + rr];
-        a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
-        bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
+        x[t] = sh.mat[ci_ * LD + rr];
+        y[t] = sh.mat[cj_ * LD + rr];
         gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
         gi = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, gi));
+        a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
+        bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
       }
       a = team_sum<TM>(a);
       bb = team_sum<TM>(bb);
       gr = team_sum<TM>(gr);
       gi = team_sum<TM>(gi);
       const double ag2 = fma(gr, gr, gi * gi);
-      if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * a * bb) {
+      const double ab = a * bb;
+      if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
         rotated = 1;
+        big |= ag2 > 1e-16 * ab;
         const double rg = rsqrt_full(ag2);                 // 1/|g|
         const double zeta = (bb - a) * 0.5 * rg;
         const double w = fma(zeta, zeta, 1.0);
@@ -189,8 +215,13 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N, double* tiny2_ou
         }
       }
       __syncthreads();
+      if (q > 0) ci = (ci == NP - 1) ? 1 : ci + 1;
+      cj = (cj == NP - 1) ? 1 : cj + 1;
     }
-    converged = !__syncthreads_or(rotated);
+    // Converged when nothing was rotated, or when every rotated pair of this sweep was already
+    // within 1e-8 of orthogonal: one-sided Jacobi converges quadratically, so the columns are
+    // then orthogonal to ~1e-16 and a verification sweep would rotate nothing.
+    converged = !__syncthreads_or(rotated & big);
   }
   for (int col = tid; col < N; col += kLayerThreads) {
     double s2 = 0.0;
@@ -205,13 +236,13 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N, double* tiny2_ou
 }
 
 template <int S, typename T>
-__device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N, double* tiny2) {
+__device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   const JShape js = jacobi_shape(M, N);
 #define ANOMPS_JT(NPV, RV)                                                           \
   if (js.NP == NPV && js.R == RV) {                                                  \
-    if constexpr (NPV <= 2 * S && RV * ((64 / (NPV / 2)) < 16 ? 64 / (NPV / 2) : 16) <= \
+    if constexpr (NPV <= 2 * S && RV * ((kLayerThreads / (NPV / 2)) < 16 ? kLayerThreads / (NPV / 2) : 16) <= \
                                        LayerShared<S, T>::LD)                        \
-      return jacobi_tile<S, T, NPV, RV>(sh, M, N, tiny2);                            \
+      return jacobi_tile<S, T, NPV, RV>(sh, M, N);                                  \
   }
 #define ANOMPS_JN(NPV) ANOMPS_JT(NPV, 1) ANOMPS_JT(NPV, 2) ANOMPS_JT(NPV, 4) ANOMPS_JT(NPV, 8)
   ANOMPS_JN(2) ANOMPS_JN(4) ANOMPS_JN(8) ANOMPS_JN(16) ANOMPS_JN(32)
@@ -223,21 +254,23 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N, double* tiny2
 // Apply U = R_Y(theta) R_Z(phi) to the physical index of the (Dl x 2 x Dr) tensor in ta.
 template <int S, typename T>
 __device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, double theta, double phi) {
+  constexpr int SP = LayerShared<S, T>::SP;
   double st, ct, sp, cp;
   sincos(0.5 * theta, &st, &ct);
   sincos(0.5 * phi, &sp, &cp);
   const cd em{cp, -sp}, ep{cp, sp};  // e^{-i phi/2}, e^{+i phi/2}
   const cd u00 = cscale(em, ct), u01 = cscale(ep, -st);
   const cd u10 = cscale(em, st), u11 = cscale(ep, ct);
+  const FastDiv fd(Dr);
   for (int idx = threadIdx.x; idx < Dl * Dr; idx += kLayerThreads) {
-    const int a = idx / Dr, b = idx % Dr;
-    const cd v0 = sh.ta[(a * 2 + 0) * S + b];
-    const cd v1 = sh.ta[(a * 2 + 1) * S + b];
+    const int a = fd.q(idx), b = fd.r(idx);
+    const cd v0 = sh.ta[(a * 2 + 0) * SP + b];
+    const cd v1 = sh.ta[(a * 2 + 1) * SP + b];
     cd w0 = cmul(u00, v0), w1 = cmul(u10, v0);
     cfma(w0, u01, v1);
     cfma(w1, u11, v1);
-    sh.ta[(a * 2 + 0) * S + b] = w0;
-    sh.ta[(a * 2 + 1) * S + b] = w1;
+    sh.ta[(a * 2 + 0) * SP + b] = w0;
+    sh.ta[(a * 2 + 1) * SP + b] = w1;
   }
   __syncthreads();
 }
@@ -247,34 +280,39 @@ __device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, double theta, 
 template <int S, typename T>
 struct SitePrefetch {
   static constexpr int PF = (2 * S * S + kLayerThreads - 1) / kLayerThreads;
+  static constexpr int SP = LayerShared<S, T>::SP;
   cx<T> v[PF];
   int Dl = 0, Dr = 0;
   __device__ void load(const T* slot, int dl, int dr) {
     Dl = dl;
     Dr = dr;
+    const FastDiv fd(Dr);
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int idx = threadIdx.x + i * kLayerThreads;
       if (idx < Dl * 2 * Dr) {
-        const int row = idx / Dr, b = idx % Dr;
+        const int row = fd.q(idx), b = fd.r(idx);
         v[i] = cx<T>{slot[2 * ((size_t)row * S + b)], slot[2 * ((size_t)row * S + b) + 1]};
       }
     }
   }
   __device__ void commit(cx<T>* dst) const {
+    const FastDiv fd(Dr);
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int idx = threadIdx.x + i * kLayerThreads;
-      if (idx < Dl * 2 * Dr) dst[(idx / Dr) * S + idx % Dr] = v[i];
+      if (idx < Dl * 2 * Dr) dst[fd.q(idx) * SP + fd.r(idx)] = v[i];
     }
   }
 };
 
 template <int S, typename T>
 __device__ void store_tensor(T* slot, const cd* src, int Dl, int Dr) {
+  constexpr int SP = LayerShared<S, T>::SP;
+  const FastDiv fd(Dr);
   for (int idx = threadIdx.x; idx < Dl * 2 * Dr; idx += kLayerThreads) {
-    const int row = idx / Dr, b = idx % Dr;
-    store_c<T, double>(slot, (size_t)row * S + b, src[row * S + b]);
+    const int row = fd.q(idx), b = fd.r(idx);
+    store_c<T, double>(slot, (size_t)row * S + b, src[row * SP + b]);
   }
 }
 
@@ -289,6 +327,7 @@ __device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int la
                             const double* theta, const double* phi, double* trunc_err,
                             int* status) {
   constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
   constexpr size_t SLOT = (size_t)2 * S * S * 2;  // T values per site slot
   const int tid = threadIdx.x;
   int flags = 0;
@@ -300,7 +339,7 @@ __device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int la
   pf.load(st + (size_t)(n - 1) * SLOT, dold(n - 2), 1);
   pf.commit(sh.tb);
   __syncthreads();
-  for (int idx = tid; idx < dold(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * S] = to_cd(sh.tb[idx * S]);
+  for (int idx = tid; idx < dold(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * SP] = to_cd(sh.tb[idx * SP]);
   __syncthreads();
   for (int k = n - 1; k >= 1; --k) {
     const int Dl = dold(k - 1), Dr = dold(k), Dll = dold(k - 2);
@@ -309,43 +348,48 @@ __device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int la
     // mat = t^H: rows (s, b) -> s*Dr + b, columns a; rows [M, MP) zero.
     const int M = 2 * Dr, N = Dl;
     const int MP = jacobi_shape(M, N).MP;
+    const FastDiv fmp(MP);
     for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-      const int a = idx / MP, rr = idx % MP;
+      const int a = fmp.q(idx), rr = fmp.r(idx);
       cd v{0.0, 0.0};
-      if (rr < M) v = cconj(sh.ta[(a * 2 + rr / Dr) * S + rr % Dr]);
+      if (rr < M) {
+        const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
+        v = cconj(sh.ta[(a * 2 + s_) * SP + b]);
+      }
       sh.mat[a * LD + rr] = v;
     }
     __syncthreads();
-    double tiny2;
-    flags |= jacobi_columns<S, T>(sh, M, N, &tiny2);
+    flags |= jacobi_columns<S, T>(sh, M, N);
+    const double tiny2 = sh.tiny2;
     // Right-canonical rows q_a^H and V*Sigma = t Q.
     T* slot = st + (size_t)k * SLOT;
+    const FastDiv fm(M), fn(N), fdl(Dl);
     for (int idx = tid; idx < N * M; idx += kLayerThreads) {
-      const int a = idx / M, rr = idx % M;
-      const int s = rr / Dr, b = rr % Dr;
+      const int a = fm.q(idx), rr = fm.r(idx);
+      const int s = rr >= Dr, b = rr - (s ? Dr : 0);
       const double s2 = sh.sig2[a];
       cd v{0.0, 0.0};
       if (s2 > tiny2) v = cscale(cconj(sh.mat[a * LD + rr]), rsqrt_full(s2));
       store_c<T, double>(slot, (size_t)(a * 2 + s) * S + b, v);
     }
     for (int idx = tid; idx < N * N; idx += kLayerThreads) {
-      const int j = idx / N, a = idx % N;
+      const int j = fn.q(idx), a = fn.r(idx);
       const double s2 = sh.sig2[a];
       cd acc{0.0, 0.0};
       if (s2 > tiny2) {
-        for (int rr = 0; rr < M; ++rr)
-          cfma(acc, sh.ta[(j * 2 + rr / Dr) * S + rr % Dr], sh.mat[a * LD + rr]);
+        for (int b = 0; b < Dr; ++b) cfma(acc, sh.ta[(j * 2) * SP + b], sh.mat[a * LD + b]);
+        for (int b = 0; b < Dr; ++b) cfma(acc, sh.ta[(j * 2 + 1) * SP + b], sh.mat[a * LD + Dr + b]);
         acc = cscale(acc, rsqrt_full(s2));
       }
-      sh.uq[j * S + a] = acc;
+      sh.uq[j * SP + a] = acc;
     }
     pf.commit(sh.tb);
     __syncthreads();
     for (int idx = tid; idx < Dll * 2 * Dl; idx += kLayerThreads) {
-      const int row = idx / Dl, a = idx % Dl;
+      const int row = fdl.q(idx), a = fdl.r(idx);
       cd acc{0.0, 0.0};
-      for (int j = 0; j < Dl; ++j) cfma(acc, to_cd(sh.tb[row * S + j]), sh.uq[j * S + a]);
-      sh.ta[row * S + a] = acc;
+      for (int j = 0; j < Dl; ++j) cfma(acc, to_cd(sh.tb[row * SP + j]), sh.uq[j * SP + a]);
+      sh.ta[row * SP + a] = acc;
     }
     __syncthreads();
   }
@@ -360,67 +404,86 @@ __device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int la
     if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, dold(k + 1), dold(k + 2));
     const int M = 2 * Dl, N = 2 * Dr;
     const int MP = jacobi_shape(M, N).MP;
-    // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR s, b]   (CNOT control k)
-    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-      const int col = idx / MP, row = idx % MP;
-      const int t = col / Dr, b = col % Dr, s = row & 1;
-      cd acc{0.0, 0.0};
-      if (row < M)
-        for (int c = 0; c < Dc; ++c) cfma(acc, sh.ta[row * S + c], to_cd(sh.tb[(c * 2 + (t ^ s)) * S + b]));
-      sh.mat[col * LD + row] = acc;
+    // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR s, b]   (CNOT control k).
+    {
+      const FastDiv fmp(MP), fdr(Dr);
+      for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
+        const int col = fmp.q(idx), row = fmp.r(idx);
+        const int t = col >= Dr, b = col - (t ? Dr : 0), s_ = row & 1;
+        cd acc{0.0, 0.0};
+        if (row < M)
+          for (int c = 0; c < Dc; ++c)
+            cfma(acc, sh.ta[row * SP + c], to_cd(sh.tb[(c * 2 + (t ^ s_)) * SP + b]));
+        sh.mat[col * LD + row] = acc;
+      }
     }
     __syncthreads();
-    double tiny2;
-    flags |= jacobi_columns<S, T>(sh, M, N, &tiny2);
+    flags |= jacobi_columns<S, T>(sh, M, N);
+    const double tiny2 = sh.tiny2;
     const int D = min(chi, min(M, N));
-    // Sort singular values (descending, ties by column index); NaN counts as zero.
-    for (int c = tid; c < N; c += kLayerThreads) {
-      double v = sh.sig2[c];
+    // Rank columns by singular value (descending, ties by index; NaN counts as zero); thread c
+    // owns column c (N <= 2S <= 64).
+    if (tid < N) {
+      double v = sh.sig2[tid];
       if (!(v >= 0.0)) v = 0.0;
-      int rank = 0;
+      int rk = 0;
       for (int i = 0; i < N; ++i) {
         double w = sh.sig2[i];
         if (!(w >= 0.0)) w = 0.0;
-        rank += (w > v) || (w == v && i < c);
+        rk += (w > v) || (w == v && i < tid);
       }
-      sh.order[rank] = c;
+      sh.rank[rk] = tid;
     }
     __syncthreads();
     double kept = 0.0, disc = 0.0;
     for (int r = 0; r < N; ++r) {
-      const double v = sh.sig2[sh.order[r]];
+      double v = sh.sig2[sh.rank[r]];
+      if (!(v >= 0.0)) v = 0.0;
       if (r < D) kept += v; else disc += v;
     }
     if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
     const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
     if (tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
     // U columns = normalised kept columns of W (numerically zero columns become zero).
-    for (int idx = tid; idx < M * D; idx += kLayerThreads) {
-      const int r = idx / D, j = idx % D;
-      const int c = sh.order[j];
-      const double s2 = sh.sig2[c];
-      cd v{0.0, 0.0};
-      if (s2 > tiny2) v = cscale(sh.mat[c * LD + r], rsqrt_full(s2));
-      sh.uq[r * S + j] = v;
+    {
+      const FastDiv fd(D);
+      for (int idx = tid; idx < M * D; idx += kLayerThreads) {
+        const int r = fd.q(idx), j = fd.r(idx);
+        const int c = sh.rank[j];
+        const double s2 = sh.sig2[c];
+        cd v{0.0, 0.0};
+        if (s2 > tiny2) v = cscale(sh.mat[c * LD + r], rsqrt_full(s2));
+        sh.uq[r * SP + j] = v;
+      }
     }
     __syncthreads();
     store_tensor<S, T>(st + (size_t)k * SLOT, sh.uq, Dl, D);
-    // X_s = U_s^H A_s  ->  mat[(s*S + j)*S + c]
-    for (int idx = tid; idx < 2 * D * Dc; idx += kLayerThreads) {
-      const int s = idx / (D * Dc), j = (idx / Dc) % D, c = idx % Dc;
-      cd acc{0.0, 0.0};
-      for (int a = 0; a < Dl; ++a) cfmac(acc, sh.uq[(a * 2 + s) * S + j], sh.ta[(a * 2 + s) * S + c]);
-      sh.mat[(s * S + j) * S + c] = acc;
+    // X_s = U_s^H A_s  ->  mat[(s*S + j)*SP + c]
+    {
+      const FastDiv fdc(Dc), fdd(D);
+      for (int idx = tid; idx < 2 * D * Dc; idx += kLayerThreads) {
+        const int sj = fdc.q(idx), c = fdc.r(idx);
+        const int s_ = sj >= D, j = sj - (s_ ? D : 0);
+        cd acc{0.0, 0.0};
+        for (int a = 0; a < Dl; ++a)
+          cfmac(acc, sh.uq[(a * 2 + s_) * SP + j], sh.ta[(a * 2 + s_) * SP + c]);
+        sh.mat[(s_ * S + j) * SP + c] = acc;
+      }
     }
     __syncthreads();
-    // New centre S V^H = U^H Theta' / |sigma_kept|  ->  ta[(j*2+t)*S + b]
-    for (int idx = tid; idx < D * 2 * Dr; idx += kLayerThreads) {
-      const int j = idx / (2 * Dr), t = (idx / Dr) & 1, b = idx % Dr;
-      cd acc{0.0, 0.0};
-      for (int s = 0; s < 2; ++s)
-        for (int c = 0; c < Dc; ++c)
-          cfma(acc, sh.mat[(s * S + j) * S + c], to_cd(sh.tb[(c * 2 + (t ^ s)) * S + b]));
-      sh.ta[(j * 2 + t) * S + b] = cscale(acc, inv_norm);
+    // New centre S V^H = U^H Theta' / |sigma_kept|  ->  ta[(j*2+t)*SP + b]
+    {
+      const FastDiv f2r(2 * Dr);
+      for (int idx = tid; idx < D * 2 * Dr; idx += kLayerThreads) {
+        const int j = f2r.q(idx), o = f2r.r(idx);
+        const int t = o >= Dr, b = o - (t ? Dr : 0);
+        cd acc{0.0, 0.0};
+        for (int c = 0; c < Dc; ++c) {
+          cfma(acc, sh.mat[j * SP + c], to_cd(sh.tb[(c * 2 + t) * SP + b]));
+          cfma(acc, sh.mat[(S + j) * SP + c], to_cd(sh.tb[(c * 2 + (t ^ 1)) * SP + b]));
+        }
+        sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
+      }
     }
     __syncthreads();
   }

@@ -67,7 +67,7 @@ def test_exact_regime_fp64(A, L):
     assert np.abs(out - ref).max() <= FP64_TOL
 
 
-@pytest.mark.parametrize("L,chi", [(2, 2), (3, 2), (3, 4), (4, 4), (4, 8)])
+@pytest.mark.parametrize("L,chi", [(2, 2), (3, 2), (3, 4), (4, 4), (4, 8), (3, 3), (4, 5), (4, 6)])
 def test_truncated_regime_fp64(A, L, chi):
     """chi < 2^L: the GPU follows the truncated oracle step by step; P5 bounds both."""
     p, n, B = 4, 16, 4
@@ -111,7 +111,7 @@ def test_l0_closed_form(A):
     assert np.abs(out - ref).max() <= 1e-14
 
 
-@pytest.mark.parametrize("L,chi", [(2, 4), (3, 8), (4, 16), (4, 2), (4, 8)])
+@pytest.mark.parametrize("L,chi", [(2, 4), (3, 8), (4, 16), (4, 2), (4, 8), (4, 12), (4, 6), (3, 5)])
 def test_49q_grid_fp32(A, L, chi):
     """7x7 blob images, complex64 contractions with FP64 SVD, small batch."""
     p, n, B = 7, 49, 3
