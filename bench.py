@@ -25,9 +25,29 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (= FP64 matrix)
-PEAK_FP32_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VALU_TFLOPS = 78.6  # FP32 vector with packed FP32 disabled (same lane count and clock)
+PEAK_FP32_MFMA_TFLOPS = 157.3  # FP32 matrix cores (dense)
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0,
+# the factors a 1 GiB device copy reads), valid only for the kernel source they were taken on.
+MEASURED_TRAFFIC = {
+    "layer": {"source": "paper_2607_10280_amd/csrc/layer.hip",
+              "sha1": "cddcf1b8bec629f1e182470fe45463770fe77fda",
+              "bytes": (2 * 37032.8 + 73786.8) * 1024},
+}
+
+
+def _measured_traffic(kernel):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != rec["sha1"]:
+            return None  # the kernel changed since the counters were taken
+    return rec["bytes"]
 
 
 def parse():
@@ -43,6 +63,9 @@ def parse():
     ap.add_argument("--plain-images", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -131,6 +154,15 @@ def main():
         anomps.ano_readout(out, coeff_d, W_d, bias_d, y)
         mark("readout")
 
+    if args.calibrate_copy_mb:
+        src = torch.empty(args.calibrate_copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -177,19 +209,28 @@ def main():
     # Roofline of the dominant kernel family.
     lay_flops = sum(workload.layer_flops(n, chi, l)["total_fp64"] for l in range(L)) * B
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
+    mfma = prec == anomps.PREC_FP32 and anomps.slot_dim(n, chi, L) == 16
     cand = {
-        "layer": (lay_flops / L, avg["layer"], PEAK_FP64_TFLOPS,
-                  "FP64 VALU: Jacobi SVD + canonical sweep, per layer launch"),
-        "measure": (meas_flops, avg["measure"],
-                    PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else PEAK_FP32_VALU_TFLOPS,
-                    "environments + pair contractions (VALU)"),
+        "layer": (lay_flops / L, avg["layer"], "alu", PEAK_FP64_TFLOPS,
+                  "FP64 VALU: Jacobi SVD + canonical sweep, per layer launch (nominal R-SVD count)"),
+        "measure": (meas_flops, avg["measure"], "mfma" if mfma else "alu",
+                    PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else
+                    (PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS),
+                    "environments + pair contractions, per measurement call"),
     }
     dom = max(cand, key=lambda k: per_step["layers" if k == "layer" else k])
-    fl, dur_ms, peak, what = cand[dom]
+    fl, dur_ms, bound, peak, what = cand[dom]
     achieved = fl / (dur_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
-                "what": what, "flops_per_launch": fl, "avg_launch_ms": round(dur_ms, 4)}
+    traffic = _measured_traffic(dom)
+    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "kernel": dom, "what": what, "flops_per_launch": fl,
+                "avg_launch_ms": round(dur_ms, 4)}
+    if dom == "layer":
+        alg = sum(workload.layer_bytes(n, chi, l, 8 if prec == anomps.PREC_FP64 else 4)
+                  for l in range(L)) / L * B
+        roofline["algorithmic_bytes_per_launch"] = round(alg)
 
     result = {
         "metric": "Pauli-feature images/sec, 49q L=4 chi=16, batched vs plain; p99 latency; max abs err",
