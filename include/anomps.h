@@ -173,6 +173,78 @@ int mps_ano_readout(const void* pauli, const void* coeff, const void* W, const v
                     int32_t batch, int32_t m, int32_t out_dim, void* y, int32_t is_f64,
                     hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Mixed requests (continuous batching).  A request is one image with its own n_sites, chi,
+ * layer count, precision, angles, pair list and buffers; a table of requests runs through one
+ * persistent launch per (slot size, precision) bucket and layer step.  The arithmetic per
+ * image is exactly that of the batch calls above (the same device code runs), so a request's
+ * results do not depend on the other requests of the table.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_sites;        /* 2 <= n <= MPS_MAX_SITES */
+  int32_t chi;            /* maximum bond dimension, >= 1 */
+  int32_t n_layers;       /* layers this request receives, >= 0 */
+  int32_t precision;      /* MPS_PREC_FP64 or MPS_PREC_FP32 */
+  int32_t n_pairs;        /* m of this request's pair list, >= 0 */
+  int32_t reserved;       /* set to 0 */
+  const double* pixels;   /* device [n_sites] float64 */
+  void* state;            /* device, >= mps_state_bytes(n_sites, chi, n_layers, 1, precision) */
+  void* env;              /* device, >= mps_env_bytes(n_sites, chi, n_layers, 1, precision) */
+  const double* theta;    /* device [n_layers][n_sites] float64 */
+  const double* phi;      /* device [n_layers][n_sites] float64 */
+  double* trunc_err;      /* device [n_layers][n_sites-1] float64, or NULL */
+  const int32_t* pairs;   /* device [n_pairs][2], checked like mps_validate_pairs */
+  void* out;              /* device [n_pairs][15]: float64 for FP64, float32 for FP32 */
+  int32_t* ctrl;          /* device [2]: ctrl[0] = layers applied so far, ctrl[1] = MPS_IMG_* flags */
+} mps_request;
+
+/* Requests are grouped by bucket = 4*(precision == FP32) + log2(S) - 1, S = mps_slot_dim(...). */
+#define MPS_MIXED_BUCKETS 8
+typedef struct {
+  int32_t n_req;
+  int32_t begin[MPS_MIXED_BUCKETS];      /* first table index of each bucket */
+  int32_t count[MPS_MIXED_BUCKETS];      /* requests in each bucket */
+  int32_t max_sites[MPS_MIXED_BUCKETS];  /* largest n_sites in each bucket */
+} mps_mixed_plan;
+
+/*
+ * Host-side planning of a request table (host pointer reqs_host; the device pointers inside
+ * are only checked for NULL).  Validates every request like the batch calls would, then writes
+ * order[t] = the index in reqs_host of the request that belongs at table position t: requests
+ * grouped by bucket, and within a bucket by decreasing estimated work (largest first, so the
+ * persistent launches finish evenly).  The caller uploads the table in that order and passes
+ * it with `plan` to the calls below.  Errors: MPS_ERR_INVALID_ARG / MPS_ERR_CAPACITY naming
+ * the first bad request; MPS_ERR_UNSUPPORTED for SPLIT_BF16 requests.
+ */
+int mps_plan_mixed(const mps_request* reqs_host, int32_t n_req, int32_t* order,
+                   mps_mixed_plan* plan);
+
+/* Encode every request of the table (mps_init_batch per request); sets ctrl = {0, flags}.
+ * reqs: device table ordered as `plan` says. */
+int mps_init_mixed(const mps_request* reqs, const mps_mixed_plan* plan, hipStream_t stream);
+
+/*
+ * Apply one more layer (mps_apply_layer) to every request of the table with
+ * ctrl[0] < n_layers, and increment its ctrl[0]; requests already done are skipped.  One
+ * persistent launch per non-empty bucket: each workgroup takes the next request from a queue
+ * counter in `queue` (device [MPS_MIXED_BUCKETS] int32, caller-owned, reset by this call with
+ * a kernel, so the call can be captured in a HIP graph).  Concurrent calls must not share
+ * `queue`.  The grid of each bucket is set by mps_set_mixed_tuning (default: what fits).
+ */
+int mps_apply_layer_mixed(const mps_request* reqs, const mps_mixed_plan* plan, int32_t* queue,
+                          hipStream_t stream);
+
+/* Environments and Pauli-pair expectations (mps_pauli_pair_expect) of every request of the
+ * table, at the layers applied so far. */
+int mps_pauli_pair_expect_mixed(const mps_request* reqs, const mps_mixed_plan* plan,
+                                hipStream_t stream);
+
+/* Persistent-grid size of a bucket's layer launch, in workgroups per compute unit
+ * (0 = the occupancy limit, the default).  Host-side setting of the calling process; the
+ * autotuner in the Python package chooses it by measurement.  MPS_ERR_INVALID_ARG for a bad
+ * bucket or a negative value. */
+int mps_set_mixed_tuning(int32_t bucket, int32_t blocks_per_cu);
+
 /* Message for the last non-OK return on the calling thread ("" if none).  The pointer stays
  * valid until the next call on that thread. */
 const char* mps_last_error(void);

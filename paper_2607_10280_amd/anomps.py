@@ -45,6 +45,38 @@ class MpsBatch(ctypes.Structure):
     ]
 
 
+class MpsRequest(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32),
+        ("chi", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("n_pairs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pixels", ctypes.c_void_p),
+        ("state", ctypes.c_void_p),
+        ("env", ctypes.c_void_p),
+        ("theta", ctypes.c_void_p),
+        ("phi", ctypes.c_void_p),
+        ("trunc_err", ctypes.c_void_p),
+        ("pairs", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("ctrl", ctypes.c_void_p),
+    ]
+
+
+MIXED_BUCKETS = 8
+
+
+class MixedPlan(ctypes.Structure):
+    _fields_ = [
+        ("n_req", ctypes.c_int32),
+        ("begin", ctypes.c_int32 * MIXED_BUCKETS),
+        ("count", ctypes.c_int32 * MIXED_BUCKETS),
+        ("max_sites", ctypes.c_int32 * MIXED_BUCKETS),
+    ]
+
+
 EXPORTS = {
     "mps_bond_dim": (ctypes.c_int32, [ctypes.c_int32] * 4),
     "mps_slot_dim": (ctypes.c_int32, [ctypes.c_int32] * 3),
@@ -60,6 +92,14 @@ EXPORTS = {
                                                              ctypes.c_int32, ctypes.c_void_p]),
     "mps_ano_readout": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 3 +
                         [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mps_plan_mixed": (ctypes.c_int, [ctypes.POINTER(MpsRequest), ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.POINTER(MixedPlan)]),
+    "mps_init_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan), ctypes.c_void_p]),
+    "mps_apply_layer_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan),
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_pauli_pair_expect_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan),
+                                                   ctypes.c_void_p]),
+    "mps_set_mixed_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "mps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -215,3 +255,42 @@ def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_
     if return_trunc_err:
         return out, b.status, te
     return out, b.status
+
+
+# ----------------------------------------------------------------------------- mixed requests
+def plan_mixed(reqs):
+    """Host planning of a list of MpsRequest: returns (order, MixedPlan); the device table must
+    hold reqs[order[0]], reqs[order[1]], ..."""
+    n = len(reqs)
+    arr = (MpsRequest * max(n, 1))(*reqs)
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    plan = MixedPlan()
+    _check(lib().mps_plan_mixed(arr, n, order.ctypes.data_as(ctypes.c_void_p), ctypes.byref(plan)))
+    return order[:n], plan
+
+
+def request_table(reqs, order, device="cuda"):
+    """Device copy of the request table in plan order (a uint8 tensor holding the structs)."""
+    import torch
+    n = len(order)
+    arr = (MpsRequest * max(n, 1))(*[reqs[i] for i in order])
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8)[: n * ctypes.sizeof(MpsRequest)].copy()
+    return torch.as_tensor(raw, device=device)
+
+
+def init_mixed(table, plan: MixedPlan, stream=None) -> None:
+    _check(lib().mps_init_mixed(_ptr(table), ctypes.byref(plan), _stream(stream)))
+
+
+def apply_layer_mixed(table, plan: MixedPlan, queue, stream=None) -> None:
+    assert queue.is_cuda and queue.numel() >= MIXED_BUCKETS
+    _check(lib().mps_apply_layer_mixed(_ptr(table), ctypes.byref(plan), _ptr(queue),
+                                       _stream(stream)))
+
+
+def pauli_pair_expect_mixed(table, plan: MixedPlan, stream=None) -> None:
+    _check(lib().mps_pauli_pair_expect_mixed(_ptr(table), ctypes.byref(plan), _stream(stream)))
+
+
+def set_mixed_tuning(bucket: int, blocks_per_cu: int) -> None:
+    _check(lib().mps_set_mixed_tuning(bucket, blocks_per_cu))

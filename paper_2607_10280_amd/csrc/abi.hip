@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,48 @@ int check_batch(const mps_batch* b) {
   int rc = check_shape(b->n_sites, b->chi, b->n_layers, b->batch, b->precision);
   if (rc) return rc;
   if (!b->state || !b->status) return fail(MPS_ERR_INVALID_ARG, "state/status pointer is NULL");
+  return MPS_OK;
+}
+
+// ---- mixed request tables
+int g_mixed_blocks_per_cu[MPS_MIXED_BUCKETS] = {0};
+
+int bucket_of(int S, int prec) {
+  int lg = 0;
+  while ((2 << lg) < S) ++lg;  // S = 2, 4, 8, 16 -> 0..3
+  return 4 * (prec == MPS_PREC_FP32 ? 1 : 0) + lg;
+}
+int bucket_slot(int bucket) { return 2 << (bucket & 3); }
+bool bucket_fp64(int bucket) { return bucket < 4; }
+
+int check_request(const mps_request& r, int idx) {
+  int rc = check_shape(r.n_sites, r.chi, r.n_layers, 1, r.precision);
+  if (rc) return fail(rc, "request %d: %s", idx, g_last_error.c_str());
+  if (r.precision == MPS_PREC_SPLIT_BF16)
+    return fail(MPS_ERR_UNSUPPORTED, "request %d: split-bf16 requests are not built in this library", idx);
+  if (r.n_pairs < 0 || r.reserved != 0)
+    return fail(MPS_ERR_INVALID_ARG, "request %d: n_pairs=%d reserved=%d", idx, r.n_pairs, r.reserved);
+  if (!r.pixels || !r.state || !r.env || !r.ctrl)
+    return fail(MPS_ERR_INVALID_ARG, "request %d: pixels/state/env/ctrl is NULL", idx);
+  if (r.n_layers > 0 && (!r.theta || !r.phi))
+    return fail(MPS_ERR_INVALID_ARG, "request %d: theta/phi is NULL", idx);
+  if (r.n_pairs > 0 && (!r.pairs || !r.out))
+    return fail(MPS_ERR_INVALID_ARG, "request %d: pairs/out is NULL", idx);
+  return MPS_OK;
+}
+
+int check_plan(const mps_request* reqs, const mps_mixed_plan* plan) {
+  if (!plan) return fail(MPS_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->n_req < 0) return fail(MPS_ERR_INVALID_ARG, "plan n_req=%d", plan->n_req);
+  int expect = 0;
+  for (int k = 0; k < MPS_MIXED_BUCKETS; ++k) {
+    if (plan->count[k] < 0 || plan->begin[k] != expect ||
+        (plan->count[k] > 0 && (plan->max_sites[k] < 2 || plan->max_sites[k] > MPS_MAX_SITES)))
+      return fail(MPS_ERR_INVALID_ARG, "plan bucket %d is inconsistent", k);
+    expect += plan->count[k];
+  }
+  if (expect != plan->n_req) return fail(MPS_ERR_INVALID_ARG, "plan counts do not sum to n_req");
+  if (plan->n_req > 0 && !reqs) return fail(MPS_ERR_INVALID_ARG, "request table is NULL");
   return MPS_OK;
 }
 
@@ -194,6 +237,103 @@ int mps_ano_readout(const void* pauli, const void* coeff, const void* W, const v
       ? launch_readout<double>((const double*)pauli, (const double*)coeff, (const double*)W, (const double*)bias, batch, m, out_dim, (double*)y, stream)
       : launch_readout<float>((const float*)pauli, (const float*)coeff, (const float*)W, (const float*)bias, batch, m, out_dim, (float*)y, stream);
   if (e != hipSuccess) return check_hip(e, "readout launch");
+  return ok();
+}
+
+int mps_plan_mixed(const mps_request* reqs_host, int32_t n_req, int32_t* order,
+                   mps_mixed_plan* plan) {
+  if (n_req < 0) return fail(MPS_ERR_INVALID_ARG, "n_req=%d < 0", n_req);
+  if (!plan || (n_req > 0 && (!reqs_host || !order)))
+    return fail(MPS_ERR_INVALID_ARG, "NULL argument");
+  std::vector<int> bucket(n_req);
+  std::vector<double> cost(n_req);
+  for (int i = 0; i < n_req; ++i) {
+    const mps_request& r = reqs_host[i];
+    int rc = check_request(r, i);
+    if (rc) return rc;
+    const int S = slot_bucket(r.n_sites, r.chi, r.n_layers);
+    bucket[i] = bucket_of(S, r.precision);
+    // Work estimate: each layer runs ~n SVDs of (2D)x(2D) matrices, D = min(chi, 2^layers).
+    const double d = (double)slot_dim(r.n_sites, r.chi, r.n_layers);
+    cost[i] = (double)r.n_layers * r.n_sites * d * d * d + r.n_sites * d * d;
+  }
+  for (int i = 0; i < n_req; ++i) order[i] = i;
+  std::stable_sort(order, order + n_req, [&](int a, int b) {
+    if (bucket[a] != bucket[b]) return bucket[a] < bucket[b];
+    return cost[a] > cost[b];
+  });
+  memset(plan, 0, sizeof(*plan));
+  plan->n_req = n_req;
+  for (int t = 0; t < n_req; ++t) {
+    const int k = bucket[order[t]];
+    if (plan->count[k]++ == 0) plan->begin[k] = t;
+    const int n = reqs_host[order[t]].n_sites;
+    if (n > plan->max_sites[k]) plan->max_sites[k] = n;
+  }
+  int at = 0;  // empty buckets start where the next one would
+  for (int k = 0; k < MPS_MIXED_BUCKETS; ++k) {
+    plan->begin[k] = at;
+    at += plan->count[k];
+  }
+  return ok();
+}
+
+int mps_init_mixed(const mps_request* reqs, const mps_mixed_plan* plan, hipStream_t stream) {
+  int rc = check_plan(reqs, plan);
+  if (rc) return rc;
+  for (int k = 0; k < MPS_MIXED_BUCKETS; ++k) {
+    if (!plan->count[k]) continue;
+    const hipError_t e = bucket_fp64(k)
+        ? launch_encode_mixed<double>(reqs, plan->begin[k], plan->count[k], bucket_slot(k), stream)
+        : launch_encode_mixed<float>(reqs, plan->begin[k], plan->count[k], bucket_slot(k), stream);
+    if (e != hipSuccess) return check_hip(e, "mixed encode launch");
+  }
+  return ok();
+}
+
+int mps_apply_layer_mixed(const mps_request* reqs, const mps_mixed_plan* plan, int32_t* queue,
+                          hipStream_t stream) {
+  int rc = check_plan(reqs, plan);
+  if (rc) return rc;
+  if (plan->n_req == 0) return ok();
+  if (!queue) return fail(MPS_ERR_INVALID_ARG, "queue is NULL");
+  hipError_t e = launch_zero_ints(queue, MPS_MIXED_BUCKETS, stream);
+  if (e != hipSuccess) return check_hip(e, "queue reset launch");
+  for (int k = 0; k < MPS_MIXED_BUCKETS; ++k) {
+    if (!plan->count[k]) continue;
+    e = bucket_fp64(k)
+        ? launch_layer_mixed<double>(reqs, plan->begin[k], plan->count[k], bucket_slot(k), queue + k,
+                                     g_mixed_blocks_per_cu[k], stream)
+        : launch_layer_mixed<float>(reqs, plan->begin[k], plan->count[k], bucket_slot(k), queue + k,
+                                    g_mixed_blocks_per_cu[k], stream);
+    if (e != hipSuccess) return check_hip(e, "mixed layer launch");
+  }
+  return ok();
+}
+
+int mps_pauli_pair_expect_mixed(const mps_request* reqs, const mps_mixed_plan* plan,
+                                hipStream_t stream) {
+  int rc = check_plan(reqs, plan);
+  if (rc) return rc;
+  for (int k = 0; k < MPS_MIXED_BUCKETS; ++k) {
+    if (!plan->count[k]) continue;
+    const int S = bucket_slot(k), b0 = plan->begin[k], c = plan->count[k], ns = plan->max_sites[k];
+    hipError_t e;
+    if (bucket_fp64(k))
+      e = launch_measure_mixed<double, double>(reqs, b0, c, ns, S, stream);
+    else if (S == 16)
+      e = launch_measure16_mixed(reqs, b0, c, ns, stream);
+    else
+      e = launch_measure_mixed<float, float>(reqs, b0, c, ns, S, stream);
+    if (e != hipSuccess) return check_hip(e, "mixed measurement launch");
+  }
+  return ok();
+}
+
+int mps_set_mixed_tuning(int32_t bucket, int32_t blocks_per_cu) {
+  if (bucket < 0 || bucket >= MPS_MIXED_BUCKETS || blocks_per_cu < 0)
+    return fail(MPS_ERR_INVALID_ARG, "bucket=%d blocks_per_cu=%d", bucket, blocks_per_cu);
+  g_mixed_blocks_per_cu[bucket] = blocks_per_cu;
   return ok();
 }
 

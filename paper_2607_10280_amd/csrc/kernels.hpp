@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/anomps.h"
+
 namespace anomps {
 
 template <typename T>
@@ -27,6 +29,20 @@ hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, i
 // Matrix-core measurement for 16-wide slots in FP32 (environments + pairs).
 hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
                             int chi, int layers, int batch, float* out, hipStream_t stream);
+
+// Mixed request tables: entries [begin, begin + count) form one bucket (slot S, precision T).
+template <typename T>
+hipError_t launch_encode_mixed(const mps_request* reqs, int begin, int count, int S,
+                               hipStream_t stream);
+template <typename T>
+hipError_t launch_layer_mixed(const mps_request* reqs, int begin, int count, int S, int* queue,
+                              int blocks_per_cu, hipStream_t stream);
+template <typename T, typename C>
+hipError_t launch_measure_mixed(const mps_request* reqs, int begin, int count, int max_sites,
+                                int S, hipStream_t stream);
+hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count, int max_sites,
+                                  hipStream_t stream);
+hipError_t launch_zero_ints(int* p, int count, hipStream_t stream);
 
 template <typename R>
 hipError_t launch_coeffs(const R* A, const R* B, const R* D, int m, R* coeff, hipStream_t stream);

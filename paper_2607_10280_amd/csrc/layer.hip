@@ -502,6 +502,122 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
                     trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b);
 }
 
+// ------------------------------------------------------------------------------- mixed requests
+// Encode: one workgroup per request of the bucket (same arithmetic as k_encode).
+template <typename T>
+__global__ void k_encode_mixed(const mps_request* reqs, int begin, int S) {
+  const mps_request& r = reqs[begin + blockIdx.x];
+  const int n = r.n_sites;
+  T* state = (T*)r.state;
+  int bad = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double x = r.pixels[k];
+    double s, c;
+    sincos(0.5 * M_PI * x, &s, &c);
+    T* slot = state + (size_t)k * (size_t)(2 * S * S) * 2;
+    store_c<T, double>(slot, 0, cd{c, 0.0});
+    store_c<T, double>(slot, S, cd{s, 0.0});
+    bad |= !isfinite(x);
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) {
+    r.ctrl[0] = 0;
+    r.ctrl[1] = bad ? kImgNonfinite : 0;
+  }
+}
+
+// One layer for every request of the bucket that still needs one.  Persistent: each workgroup
+// (one wavefront) takes the next table entry from the bucket's queue counter until the table
+// is exhausted, so every wave leaves the loop once the counter passes the bucket size.
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request* reqs, int begin,
+                                                               int count, int* queue) {
+  __shared__ LayerShared<S, T> sh;
+  for (;;) {
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(queue, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= count) break;
+    const mps_request& r = reqs[begin + t];
+    const int n = r.n_sites, layer = r.ctrl[0];
+    if (layer < 0 || layer >= r.n_layers) continue;
+    layer_chain<S, T>(sh, (T*)r.state, n, r.chi, layer, r.theta + (size_t)layer * n,
+                      r.phi + (size_t)layer * n,
+                      r.trunc_err ? r.trunc_err + (size_t)layer * (n - 1) : nullptr, r.ctrl + 1);
+    __syncthreads();
+    if (threadIdx.x == 0) r.ctrl[0] = layer + 1;
+  }
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int count, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, stream, p, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_encode_mixed(const mps_request* reqs, int begin, int count, int S,
+                               hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encode_mixed<T>, dim3(count), dim3(64), 0, stream, reqs, begin, S);
+  return hipGetLastError();
+}
+
+namespace {
+// Workgroups per CU that fit (LDS and registers) for a layer kernel, cached per kernel.
+template <int S, typename T>
+int layer_mixed_fit() {
+  static int fit = 0;
+  if (fit == 0) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_layer_mixed<S, T>, kLayerThreads, 0) !=
+            hipSuccess || blocks < 1)
+      blocks = 1;
+    fit = blocks;
+  }
+  return fit;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 1;
+  }
+  return cus;
+}
+
+template <int S, typename T>
+hipError_t launch_layer_mixed_s(const mps_request* reqs, int begin, int count, int* queue,
+                                int blocks_per_cu, hipStream_t stream) {
+  const int fit = layer_mixed_fit<S, T>();
+  const int per_cu = (blocks_per_cu > 0 && blocks_per_cu < fit) ? blocks_per_cu : fit;
+  long long grid = (long long)per_cu * device_cus();
+  if (grid > count) grid = count;
+  hipLaunchKernelGGL((k_layer_mixed<S, T>), dim3((unsigned)grid), dim3(kLayerThreads), 0, stream,
+                     reqs, begin, count, queue);
+  return hipGetLastError();
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_layer_mixed(const mps_request* reqs, int begin, int count, int S, int* queue,
+                              int blocks_per_cu, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  switch (S) {
+    case 2: return launch_layer_mixed_s<2, T>(reqs, begin, count, queue, blocks_per_cu, stream);
+    case 4: return launch_layer_mixed_s<4, T>(reqs, begin, count, queue, blocks_per_cu, stream);
+    case 8: return launch_layer_mixed_s<8, T>(reqs, begin, count, queue, blocks_per_cu, stream);
+    case 16: return launch_layer_mixed_s<16, T>(reqs, begin, count, queue, blocks_per_cu, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ------------------------------------------------------------------------------- launchers
 template <typename T>
 hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch, int* status,
@@ -531,5 +647,9 @@ template hipError_t launch_layer<double>(double*, int, int, int, int, int, const
                                          const double*, double*, int*, hipStream_t);
 template hipError_t launch_layer<float>(float*, int, int, int, int, int, const double*,
                                         const double*, double*, int*, hipStream_t);
+template hipError_t launch_encode_mixed<double>(const mps_request*, int, int, int, hipStream_t);
+template hipError_t launch_encode_mixed<float>(const mps_request*, int, int, int, hipStream_t);
+template hipError_t launch_layer_mixed<double>(const mps_request*, int, int, int, int*, int, hipStream_t);
+template hipError_t launch_layer_mixed<float>(const mps_request*, int, int, int, int*, int, hipStream_t);
 
 }  // namespace anomps

@@ -29,17 +29,15 @@ __device__ void load_site(cx<C>* dst, const T* slot, int Dl, int Dr) {
 }
 
 // ------------------------------------------------------------------------- environments
+// One image: st = its n slots, ev = its environment block of this side ([n+1][S][S]).
 template <int S, typename T, typename C>
-__global__ __launch_bounds__(kMeasThreads) void k_env(const T* state, C* env, int n, int chi,
-                                                      int layers) {
+__device__ void env_image(const T* st, C* ev, int n, int chi, int layers, int side) {
   using cc = cx<C>;
   __shared__ cc E[S * S];
   __shared__ cc A[2 * S * S];
   __shared__ cc Tm[2 * S * S];
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
-  const int b = blockIdx.x >> 1, side = blockIdx.x & 1, tid = threadIdx.x;
-  const T* st = state + (size_t)b * n * SLOT;
-  C* ev = env + (size_t)b * 2 * (n + 1) * S * S * 2 + (size_t)side * (n + 1) * S * S * 2;
+  const int tid = threadIdx.x;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
   auto store_env = [&](int k, int D) {
     for (int idx = tid; idx < D * D; idx += kMeasThreads) {
@@ -102,6 +100,15 @@ __global__ __launch_bounds__(kMeasThreads) void k_env(const T* state, C* env, in
   }
 }
 
+template <int S, typename T, typename C>
+__global__ __launch_bounds__(kMeasThreads) void k_env(const T* state, C* env, int n, int chi,
+                                                      int layers) {
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  const int b = blockIdx.x >> 1, side = blockIdx.x & 1;
+  env_image<S, T, C>(state + (size_t)b * n * SLOT,
+                     env + ((size_t)b * 2 + side) * (n + 1) * S * S * 2, n, chi, layers, side);
+}
+
 // ------------------------------------------------------------------------- pairs
 // Pauli matrix entry (P_a)[r][c], a in I,X,Y,Z.
 template <typename C>
@@ -117,10 +124,11 @@ __device__ __forceinline__ cx<C> pauli_entry(int a, int r, int c) {
 // blocks of a Hermitian-structured 2x2 block family stored as 00, 01, 11 (10 = 01^H)
 __device__ __forceinline__ int blk_of(int s, int sp) { return s + sp; }  // 00->0, 01->1, 11->2
 
+// One image and one start site i: st = its n slots, ev = its environments ([2][n+1][S][S]),
+// out = its [m][15] outputs.
 template <int S, typename T, typename C>
-__global__ __launch_bounds__(kMeasThreads) void k_pairs(const T* state, const C* env,
-                                                        const int* pairs, int m, int n, int chi,
-                                                        int layers, C* out) {
+__device__ void pairs_image(const T* st, const C* ev, const int* pairs, int m, int n, int chi,
+                            int layers, int i, C* out) {
   using cc = cx<C>;
   __shared__ cc F[3 * S * S];
   __shared__ cc A[2 * S * S];
@@ -131,13 +139,11 @@ __global__ __launch_bounds__(kMeasThreads) void k_pairs(const T* state, const C*
   __shared__ int cnt;
   __shared__ C rho[32];
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
-  const int i = blockIdx.x % (n - 1), b = blockIdx.x / (n - 1), tid = threadIdx.x;
-  const T* st = state + (size_t)b * n * SLOT;
-  const C* ev = env + (size_t)b * 2 * (n + 1) * S * S * 2;
+  const int tid = threadIdx.x;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
   const C qnan = (C)__builtin_nan("");
   auto nan_out = [&](int q) {
-    for (int al = 0; al < 15; ++al) out[((size_t)b * m + q) * 15 + al] = qnan;
+    for (int al = 0; al < 15; ++al) out[(size_t)q * 15 + al] = qnan;
   };
 
   if (tid == 0) cnt = 0;
@@ -278,10 +284,60 @@ __global__ __launch_bounds__(kMeasThreads) void k_pairs(const T* state, const C*
         const cc w = cmul(pauli_entry<C>(pa, sp, s), pauli_entry<C>(pc, tp, t));
         acc += r.re * w.re - r.im * w.im;
       }
-      out[((size_t)b * m + q) * 15 + tid] = acc;
+      out[(size_t)q * 15 + tid] = acc;
     }
     __syncthreads();
   }
+}
+
+template <int S, typename T, typename C>
+__global__ __launch_bounds__(kMeasThreads) void k_pairs(const T* state, const C* env,
+                                                        const int* pairs, int m, int n, int chi,
+                                                        int layers, C* out) {
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  const int i = blockIdx.x % (n - 1), b = blockIdx.x / (n - 1);
+  pairs_image<S, T, C>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * S * S * 2,
+                       pairs, m, n, chi, layers, i, out + (size_t)b * m * 15);
+}
+
+// ------------------------------------------------------------------------- mixed requests
+// Table entries [begin, begin + count) share the slot size S and the precision.  Environments:
+// one workgroup per (request, side); pairs: one per (request, start site), the grid sized for
+// the bucket's largest chain (workgroups past a request's last start site exit at once).
+template <int S, typename T, typename C>
+__global__ __launch_bounds__(kMeasThreads) void k_env_mixed(const mps_request* reqs, int begin) {
+  const mps_request& r = reqs[begin + (blockIdx.x >> 1)];
+  const int side = blockIdx.x & 1, n = r.n_sites;
+  env_image<S, T, C>((const T*)r.state, (C*)r.env + (size_t)side * (n + 1) * S * S * 2, n, r.chi,
+                     r.ctrl[0], side);
+}
+
+template <int S, typename T, typename C>
+__global__ __launch_bounds__(kMeasThreads) void k_pairs_mixed(const mps_request* reqs, int begin,
+                                                              int max_sites) {
+  const mps_request& r = reqs[begin + blockIdx.x / (max_sites - 1)];
+  const int i = blockIdx.x % (max_sites - 1), n = r.n_sites;
+  if (i >= n - 1 || r.n_pairs == 0) return;
+  pairs_image<S, T, C>((const T*)r.state, (const C*)r.env, r.pairs, r.n_pairs, n, r.chi, r.ctrl[0],
+                       i, (C*)r.out);
+}
+
+template <typename T, typename C>
+hipError_t launch_measure_mixed(const mps_request* reqs, int begin, int count, int max_sites,
+                                int S, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const dim3 ge(2 * count), gp((unsigned)((size_t)count * (max_sites - 1))), block(kMeasThreads);
+  switch (S) {
+#define ANOMPS_MM(SV)                                                                          \
+  case SV:                                                                                     \
+    hipLaunchKernelGGL((k_env_mixed<SV, T, C>), ge, block, 0, stream, reqs, begin);           \
+    hipLaunchKernelGGL((k_pairs_mixed<SV, T, C>), gp, block, 0, stream, reqs, begin, max_sites); \
+    break;
+    ANOMPS_MM(2) ANOMPS_MM(4) ANOMPS_MM(8) ANOMPS_MM(16)
+#undef ANOMPS_MM
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------- launchers
@@ -318,5 +374,7 @@ template hipError_t launch_envs<double, double>(const double*, double*, int, int
 template hipError_t launch_envs<float, float>(const float*, float*, int, int, int, int, int, hipStream_t);
 template hipError_t launch_pairs<double, double>(const double*, const double*, const int*, int, int, int, int, int, int, double*, hipStream_t);
 template hipError_t launch_pairs<float, float>(const float*, const float*, const int*, int, int, int, int, int, int, float*, hipStream_t);
+template hipError_t launch_measure_mixed<double, double>(const mps_request*, int, int, int, int, hipStream_t);
+template hipError_t launch_measure_mixed<float, float>(const mps_request*, int, int, int, int, hipStream_t);
 
 }  // namespace anomps

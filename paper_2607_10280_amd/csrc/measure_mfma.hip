@@ -132,18 +132,13 @@ __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4]
 }  // namespace
 
 // ------------------------------------------------------------------------- environments
-__global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int n, int chi,
-                                              int layers, int batch) {
+// One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).
+__device__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
   __shared__ cf at[2 * 16 * TS];
   __shared__ cf E[16 * TS];
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
-  const int b = NXCD * (j >> 1) + xcd, side = j & 1;
-  if (b >= batch) return;
   const int l = threadIdx.x;
-  const float* st = state + (size_t)b * n * SLOT;
-  float* ev = env + ((size_t)b * 2 + side) * (n + 1) * ETILE;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
   for (int idx = l; idx < 16 * TS; idx += W) E[idx] = cf{0.f, 0.f};
   if (l == 0) E[0] = cf{1.f, 0.f};
@@ -213,9 +208,10 @@ __device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
   }
 }
 
-__global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* env,
-                                                const int* pairs, int m, int n, int chi,
-                                                int layers, int batch, float* out) {
+// One image and one start site i: st = its n slots, evL = its environments ([2][n+1][16][16]),
+// out = its [m][15] outputs.
+__device__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
+                              int chi, int layers, int i, float* out) {
   __shared__ cf F[3][16 * TS];
   __shared__ cf at[2 * 16 * TS];
   __shared__ cf Ev[16 * TS];
@@ -224,12 +220,7 @@ __global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* 
   __shared__ float rho[32];
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
-  const int b = NXCD * (jw / (n - 1)) + xcd, i = jw % (n - 1);
-  if (b >= batch) return;
   const int l = threadIdx.x, g = l >> 4, lj = l & 15;
-  const float* st = state + (size_t)b * n * SLOT;
-  const float* evL = env + (size_t)b * 2 * (n + 1) * ETILE;
   const float* evR = evL + (size_t)(n + 1) * ETILE;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
   const float qnan = __builtin_nanf("");
@@ -245,10 +236,10 @@ __global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* 
         tq[slot] = q;
         tj[slot] = pj;
       } else {
-        for (int al = 0; al < 15; ++al) out[((size_t)b * m + q) * 15 + al] = qnan;
+        for (int al = 0; al < 15; ++al) out[(size_t)q * 15 + al] = qnan;
       }
     } else if (!valid && i == 0) {
-      for (int al = 0; al < 15; ++al) out[((size_t)b * m + q) * 15 + al] = qnan;
+      for (int al = 0; al < 15; ++al) out[(size_t)q * 15 + al] = qnan;
     }
   }
   __syncthreads();
@@ -407,10 +398,70 @@ __global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* 
         const float wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
         acc += rho[2 * e] * wr - rho[2 * e + 1] * wi;
       }
-      out[((size_t)b * m + q) * 15 + l] = acc;
+      out[(size_t)q * 15 + l] = acc;
     }
     __syncthreads();
   }
+}
+
+// Workgroup w runs on XCD w % 8; all workgroups of one image sit on the same XCD so that its
+// state and environments are shared through that XCD's L2.
+__global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int n, int chi,
+                                              int layers, int batch) {
+  constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
+  constexpr size_t ETILE = (size_t)16 * 16 * 2;
+  const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
+  const int b = NXCD * (j >> 1) + xcd, side = j & 1;
+  if (b >= batch) return;
+  env16_image(state + (size_t)b * n * SLOT, env + ((size_t)b * 2 + side) * (n + 1) * ETILE, n, chi,
+              layers, side);
+}
+
+__global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* env,
+                                                const int* pairs, int m, int n, int chi,
+                                                int layers, int batch, float* out) {
+  constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
+  constexpr size_t ETILE = (size_t)16 * 16 * 2;
+  const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
+  const int b = NXCD * (jw / (n - 1)) + xcd, i = jw % (n - 1);
+  if (b >= batch) return;
+  pairs16_image(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs, m, n,
+                chi, layers, i, out + (size_t)b * m * 15);
+}
+
+// Mixed request tables (one bucket: S = 16, FP32), with the same XCD grouping by request.
+__global__ __launch_bounds__(W) void k_env16_mixed(const mps_request* reqs, int begin, int count) {
+  constexpr size_t ETILE = (size_t)16 * 16 * 2;
+  const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
+  const int r = NXCD * (j >> 1) + xcd, side = j & 1;
+  if (r >= count) return;
+  const mps_request& q = reqs[begin + r];
+  const int n = q.n_sites;
+  env16_image((const float*)q.state, (float*)q.env + (size_t)side * (n + 1) * ETILE, n, q.chi,
+              q.ctrl[0], side);
+}
+
+__global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, int begin, int count,
+                                                      int max_sites) {
+  const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
+  const int r = NXCD * (jw / (max_sites - 1)) + xcd, i = jw % (max_sites - 1);
+  if (r >= count) return;
+  const mps_request& q = reqs[begin + r];
+  const int n = q.n_sites;
+  if (i >= n - 1 || q.n_pairs == 0) return;
+  pairs16_image((const float*)q.state, (const float*)q.env, q.pairs, q.n_pairs, n, q.chi,
+                q.ctrl[0], i, (float*)q.out);
+}
+
+hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count, int max_sites,
+                                  hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const int groups = (count + NXCD - 1) / NXCD;
+  hipLaunchKernelGGL(k_env16_mixed, dim3((unsigned)(NXCD * groups * 2)), dim3(W), 0, stream, reqs,
+                     begin, count);
+  hipLaunchKernelGGL(k_pairs16_mixed, dim3((unsigned)((size_t)NXCD * groups * (max_sites - 1))),
+                     dim3(W), 0, stream, reqs, begin, count, max_sites);
+  return hipGetLastError();
 }
 
 hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,

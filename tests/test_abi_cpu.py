@@ -76,3 +76,42 @@ def test_neighbour_pairs_layout():
     assert tuple(p[0]) == (0, 1) and tuple(p[41]) == (47, 48) and tuple(p[42]) == (0, 7)
     assert np.all(p[:42, 1] - p[:42, 0] == 1) and np.all(p[42:, 1] - p[42:, 0] == 7)
     assert inputs.neighbour_pairs(16).shape == (480, 2)
+
+
+def _req(n, chi, L, prec, m=4, ptr=0x1000):
+    return anomps.MpsRequest(n, chi, L, prec, m, 0, ptr, ptr, ptr, ptr, ptr, 0, ptr, ptr, ptr)
+
+
+def test_plan_mixed_groups_buckets_and_orders_by_work():
+    reqs = [_req(16, 4, 1, anomps.PREC_FP32), _req(49, 16, 4, anomps.PREC_FP32),
+            _req(9, 2, 3, anomps.PREC_FP64), _req(36, 16, 2, anomps.PREC_FP32),
+            _req(64, 16, 2, anomps.PREC_FP32), _req(49, 16, 3, anomps.PREC_FP64)]
+    order, plan = anomps.plan_mixed(reqs)
+    assert sorted(order) == list(range(len(reqs)))
+    slot = lambda r: anomps.slot_dim(r.n_sites, r.chi, r.n_layers)
+    bucket = lambda r: 4 * (r.precision == anomps.PREC_FP32) + int(np.log2(slot(r))) - 1
+    seq = [bucket(reqs[i]) for i in order]
+    assert seq == sorted(seq)
+    assert plan.n_req == len(reqs)
+    for k in range(anomps.MIXED_BUCKETS):
+        members = [reqs[i] for i in order[plan.begin[k]:plan.begin[k] + plan.count[k]]]
+        assert all(bucket(r) == k for r in members)
+        if members:
+            assert plan.max_sites[k] == max(r.n_sites for r in members)
+    # within the S=4 FP32 bucket the 64-site request (more work) comes before the 36-site one
+    b4 = [reqs[i].n_sites for i in order[plan.begin[5]:plan.begin[5] + plan.count[5]]]
+    assert b4 == [64, 36]
+
+
+def test_plan_mixed_rejects_bad_requests():
+    with pytest.raises(anomps.MpsError) as e:
+        anomps.plan_mixed([_req(16, 4, 1, anomps.PREC_FP32), _req(16, 4, 1, anomps.PREC_FP32, ptr=0)])
+    assert e.value.code == -1 and "request 1" in str(e.value)
+    with pytest.raises(anomps.MpsError) as e:
+        anomps.plan_mixed([_req(16, 4, 1, anomps.PREC_SPLIT_BF16)])
+    assert e.value.code == -4
+    with pytest.raises(anomps.MpsError) as e:
+        anomps.plan_mixed([_req(64, 32, 5, anomps.PREC_FP32)])
+    assert e.value.code == -2
+    order, plan = anomps.plan_mixed([])
+    assert len(order) == 0 and plan.n_req == 0
