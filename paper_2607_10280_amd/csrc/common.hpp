@@ -33,6 +33,17 @@ __host__ __device__ inline int slot_dim(int n, int chi, int layers) {
   return s;
 }
 
+// Wave-uniform copies (SGPRs) of values every lane loaded from the same address, so that the
+// control flow they steer compiles to scalar branches.
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
+
 // Minimal complex arithmetic on (re, im) pairs.
 template <typename R>
 struct cx {

@@ -323,7 +323,7 @@ __device__ __forceinline__ cd to_cd(cx<T> v) {
 
 // Applies layer `layer` (0-based) to one image whose n slots start at `st`.
 template <int S, typename T>
-__device__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
+__device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
                             const double* theta, const double* phi, double* trunc_err,
                             int* status) {
   constexpr int LD = LayerShared<S, T>::LD;
@@ -506,12 +506,14 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
 // Encode: one workgroup per request of the bucket (same arithmetic as k_encode).
 template <typename T>
 __global__ void k_encode_mixed(const mps_request* reqs, int begin, int S) {
-  const mps_request& r = reqs[begin + blockIdx.x];
-  const int n = r.n_sites;
-  T* state = (T*)r.state;
+  const mps_request* r = reqs + begin + blockIdx.x;
+  const int n = uniform_int(r->n_sites);
+  T* state = uniform_ptr((T*)r->state);
+  const double* pixels = uniform_ptr(r->pixels);
+  int32_t* ctrl = uniform_ptr(r->ctrl);
   int bad = 0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double x = r.pixels[k];
+    const double x = pixels[k];
     double s, c;
     sincos(0.5 * M_PI * x, &s, &c);
     T* slot = state + (size_t)k * (size_t)(2 * S * S) * 2;
@@ -521,31 +523,39 @@ __global__ void k_encode_mixed(const mps_request* reqs, int begin, int S) {
   }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) {
-    r.ctrl[0] = 0;
-    r.ctrl[1] = bad ? kImgNonfinite : 0;
+    ctrl[0] = 0;
+    ctrl[1] = bad ? kImgNonfinite : 0;
   }
 }
 
 // One layer for every request of the bucket that still needs one.  Persistent: each workgroup
 // (one wavefront) takes the next table entry from the bucket's queue counter until the table
 // is exhausted, so every wave leaves the loop once the counter passes the bucket size.
+// Every value that steers control flow is made wave-uniform with readfirstlane, so the loop
+// and everything in layer_chain compile to scalar branches as in k_layer.  The ticket is taken
+// without a lane-dependent branch (all lanes issue the add, only lane 0 adds 1): with a branch
+// around the atomic, the compiler may specialise the loop for the lanes that skip it and fold
+// their readfirstlane to a constant, after which those lanes never see the queue advance.
 template <int S, typename T>
 __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request* reqs, int begin,
                                                                int count, int* queue) {
   __shared__ LayerShared<S, T> sh;
   for (;;) {
-    int t = 0;
-    if (threadIdx.x == 0) t = atomicAdd(queue, 1);
-    t = __builtin_amdgcn_readfirstlane(t);
+    const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
+    const int t = __builtin_amdgcn_readfirstlane(ticket);
     if (t >= count) break;
-    const mps_request& r = reqs[begin + t];
-    const int n = r.n_sites, layer = r.ctrl[0];
-    if (layer < 0 || layer >= r.n_layers) continue;
-    layer_chain<S, T>(sh, (T*)r.state, n, r.chi, layer, r.theta + (size_t)layer * n,
-                      r.phi + (size_t)layer * n,
-                      r.trunc_err ? r.trunc_err + (size_t)layer * (n - 1) : nullptr, r.ctrl + 1);
+    const mps_request* r = reqs + begin + t;
+    int32_t* ctrl = uniform_ptr(r->ctrl);
+    const int n = uniform_int(r->n_sites), chi = uniform_int(r->chi);
+    const int n_layers = uniform_int(r->n_layers), layer = uniform_int(ctrl[0]);
+    if (layer < 0 || layer >= n_layers) continue;
+    const double* theta = uniform_ptr(r->theta) + (size_t)layer * n;
+    const double* phi = uniform_ptr(r->phi) + (size_t)layer * n;
+    double* te = uniform_ptr(r->trunc_err);
+    layer_chain<S, T>(sh, uniform_ptr((T*)r->state), n, chi, layer, theta, phi,
+                      te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1);
     __syncthreads();
-    if (threadIdx.x == 0) r.ctrl[0] = layer + 1;
+    if (threadIdx.x == 0) ctrl[0] = layer + 1;
   }
 }
 

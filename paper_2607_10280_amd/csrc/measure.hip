@@ -31,7 +31,7 @@ __device__ void load_site(cx<C>* dst, const T* slot, int Dl, int Dr) {
 // ------------------------------------------------------------------------- environments
 // One image: st = its n slots, ev = its environment block of this side ([n+1][S][S]).
 template <int S, typename T, typename C>
-__device__ void env_image(const T* st, C* ev, int n, int chi, int layers, int side) {
+__device__ __forceinline__ void env_image(const T* st, C* ev, int n, int chi, int layers, int side) {
   using cc = cx<C>;
   __shared__ cc E[S * S];
   __shared__ cc A[2 * S * S];
@@ -127,7 +127,7 @@ __device__ __forceinline__ int blk_of(int s, int sp) { return s + sp; }  // 00->
 // One image and one start site i: st = its n slots, ev = its environments ([2][n+1][S][S]),
 // out = its [m][15] outputs.
 template <int S, typename T, typename C>
-__device__ void pairs_image(const T* st, const C* ev, const int* pairs, int m, int n, int chi,
+__device__ __forceinline__ void pairs_image(const T* st, const C* ev, const int* pairs, int m, int n, int chi,
                             int layers, int i, C* out) {
   using cc = cx<C>;
   __shared__ cc F[3 * S * S];
@@ -306,20 +306,25 @@ __global__ __launch_bounds__(kMeasThreads) void k_pairs(const T* state, const C*
 // the bucket's largest chain (workgroups past a request's last start site exit at once).
 template <int S, typename T, typename C>
 __global__ __launch_bounds__(kMeasThreads) void k_env_mixed(const mps_request* reqs, int begin) {
-  const mps_request& r = reqs[begin + (blockIdx.x >> 1)];
-  const int side = blockIdx.x & 1, n = r.n_sites;
-  env_image<S, T, C>((const T*)r.state, (C*)r.env + (size_t)side * (n + 1) * S * S * 2, n, r.chi,
-                     r.ctrl[0], side);
+  const mps_request* r = reqs + begin + (blockIdx.x >> 1);
+  const int side = blockIdx.x & 1, n = uniform_int(r->n_sites);
+  const int layers = uniform_int(uniform_ptr(r->ctrl)[0]);
+  env_image<S, T, C>(uniform_ptr((const T*)r->state),
+                     uniform_ptr((C*)r->env) + (size_t)side * (n + 1) * S * S * 2, n,
+                     uniform_int(r->chi), layers, side);
 }
 
 template <int S, typename T, typename C>
 __global__ __launch_bounds__(kMeasThreads) void k_pairs_mixed(const mps_request* reqs, int begin,
                                                               int max_sites) {
-  const mps_request& r = reqs[begin + blockIdx.x / (max_sites - 1)];
-  const int i = blockIdx.x % (max_sites - 1), n = r.n_sites;
-  if (i >= n - 1 || r.n_pairs == 0) return;
-  pairs_image<S, T, C>((const T*)r.state, (const C*)r.env, r.pairs, r.n_pairs, n, r.chi, r.ctrl[0],
-                       i, (C*)r.out);
+  const mps_request* r = reqs + begin + blockIdx.x / (max_sites - 1);
+  const int i = blockIdx.x % (max_sites - 1), n = uniform_int(r->n_sites);
+  const int m = uniform_int(r->n_pairs);
+  if (i >= n - 1 || m == 0) return;
+  const int layers = uniform_int(uniform_ptr(r->ctrl)[0]);
+  pairs_image<S, T, C>(uniform_ptr((const T*)r->state), uniform_ptr((const C*)r->env),
+                       uniform_ptr(r->pairs), m, n, uniform_int(r->chi), layers, i,
+                       uniform_ptr((C*)r->out));
 }
 
 template <typename T, typename C>

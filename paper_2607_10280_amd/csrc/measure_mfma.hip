@@ -133,7 +133,7 @@ __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4]
 
 // ------------------------------------------------------------------------- environments
 // One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).
-__device__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
+__device__ __forceinline__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
   __shared__ cf at[2 * 16 * TS];
   __shared__ cf E[16 * TS];
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
@@ -210,7 +210,7 @@ __device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
 
 // One image and one start site i: st = its n slots, evL = its environments ([2][n+1][16][16]),
 // out = its [m][15] outputs.
-__device__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
+__device__ __forceinline__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
                               int chi, int layers, int i, float* out) {
   __shared__ cf F[3][16 * TS];
   __shared__ cf at[2 * 16 * TS];
@@ -435,10 +435,11 @@ __global__ __launch_bounds__(W) void k_env16_mixed(const mps_request* reqs, int 
   const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
   const int r = NXCD * (j >> 1) + xcd, side = j & 1;
   if (r >= count) return;
-  const mps_request& q = reqs[begin + r];
-  const int n = q.n_sites;
-  env16_image((const float*)q.state, (float*)q.env + (size_t)side * (n + 1) * ETILE, n, q.chi,
-              q.ctrl[0], side);
+  const mps_request* q = reqs + begin + r;
+  const int n = uniform_int(q->n_sites), layers = uniform_int(uniform_ptr(q->ctrl)[0]);
+  env16_image(uniform_ptr((const float*)q->state),
+              uniform_ptr((float*)q->env) + (size_t)side * (n + 1) * ETILE, n, uniform_int(q->chi),
+              layers, side);
 }
 
 __global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, int begin, int count,
@@ -446,11 +447,13 @@ __global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, in
   const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
   const int r = NXCD * (jw / (max_sites - 1)) + xcd, i = jw % (max_sites - 1);
   if (r >= count) return;
-  const mps_request& q = reqs[begin + r];
-  const int n = q.n_sites;
-  if (i >= n - 1 || q.n_pairs == 0) return;
-  pairs16_image((const float*)q.state, (const float*)q.env, q.pairs, q.n_pairs, n, q.chi,
-                q.ctrl[0], i, (float*)q.out);
+  const mps_request* q = reqs + begin + r;
+  const int n = uniform_int(q->n_sites), m = uniform_int(q->n_pairs);
+  if (i >= n - 1 || m == 0) return;
+  const int layers = uniform_int(uniform_ptr(q->ctrl)[0]);
+  pairs16_image(uniform_ptr((const float*)q->state), uniform_ptr((const float*)q->env),
+                uniform_ptr(q->pairs), m, n, uniform_int(q->chi), layers, i,
+                uniform_ptr((float*)q->out));
 }
 
 hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count, int max_sites,
