@@ -63,6 +63,12 @@ def parse():
     ap.add_argument("--plain-images", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve"],
+                    help="headline: the 7x7 L=4 chi=16 batch; mixed: 4096 requests of mixed size "
+                         "and depth through the persistent mixed-table launches; serve: Poisson "
+                         "arrivals through the continuous-batching loop")
+    ap.add_argument("--requests", type=int, default=0, help="mixed/serve: number of requests")
+    ap.add_argument("--tune-cache", default="", help="mixed/serve: autotuner JSON cache path")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, to scale hardware byte counters)")
@@ -101,12 +107,185 @@ def cpu_baseline(x, th, ph, pairs, chi, sample):
                              f"{per_image:.2f} s per image per core"}
 
 
+# ----------------------------------------------------------------------------- mixed / serve
+def _specs(mix, prec):
+    from paper_2607_10280_amd import inputs, mixed
+    specs = []
+    for q in mix:
+        p, L = q["p"], q["layers"]
+        x = inputs.blob_image(p, q["image_seed"])
+        th, ph = inputs.layer_angles(L, p * p, q["angle_seed"])
+        specs.append(mixed.RequestSpec(x, th, ph, inputs.neighbour_pairs(p), q["chi"], prec))
+    return specs
+
+
+def _tune(specs, args):
+    from paper_2607_10280_amd import autotune
+    if args.tune_cache and autotune.load_and_apply(args.tune_cache):
+        return {"source": args.tune_cache}
+    sample = specs[: min(len(specs), 2048)]
+    choice = autotune.tune(sample)
+    if args.tune_cache:
+        autotune.save(choice, args.tune_cache)
+    return {str(b): {"blocks_per_cu": c[0], "ms": round(c[1], 3)} for b, c in choice.items()}
+
+
+def run_mixed(args):
+    """4096 requests, p in {6,8,10,12}, L in {1,2}, chi = 16, complex64 + FP64 SVD: the whole
+    table through init, the layer steps and the measurement, eager and as one HIP graph, against
+    one request per call."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs, mixed
+    from oracle import features as ofeat
+    N = args.requests or 4096
+    prec = anomps.PRECISIONS[args.precision]
+    specs = _specs(inputs.request_mix(N, [6, 8, 10, 12], [1, 2], [16], 4), prec)
+    tuning = _tune(specs, args)
+    mr = mixed.MixedRequests(specs)
+    mr.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        mr.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    outs = mr.outputs()
+    # the same sequence captured once and replayed
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            mr.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / args.steps
+    graph_same = all(np.array_equal(a, b) for a, b in zip(outs, mr.outputs()))
+    # one request per call, and batch invariance on a sample
+    rng = np.random.Generator(np.random.PCG64(11))
+    sample = rng.choice(N, size=min(N, args.plain_images * 4), replace=False)
+    same = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in sample:
+        sp = specs[i]
+        o, _ = anomps.extract_features(sp.pixels[None], sp.theta, sp.phi, sp.pairs, sp.chi, prec)
+        same += int(np.array_equal(o.cpu().numpy()[0], outs[i]))
+    plain_s = (time.perf_counter() - t) / len(sample)
+    small = [i for i in sample if specs[i].n <= 64][:4]
+    err = max(float(np.abs(outs[i] - ofeat.exact_features(specs[i].pixels[None], specs[i].theta,
+                                                           specs[i].phi, specs[i].pairs)[0]).max())
+              for i in small)
+    ctrl = mr.ctrl()
+    result = {
+        "metric": "mixed-request images/sec (4096 requests, p in {6,8,10,12}, L in {1,2}, chi=16)",
+        "value": round(N / (ms * 1e-3), 1), "unit": "images/s", "n_gpus": 1,
+        "steps": args.steps, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"{N} mixed requests, Gaussian blobs, p~U{{6,8,10,12}}, "
+                               f"L~U{{1,2}}, chi=16, H+V pairs", "requests": N},
+        "graph": {"images_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4),
+                  "identical_to_eager": bool(graph_same)},
+        "plain": {"images_per_s": round(1.0 / plain_s, 1), "requests_timed": int(len(sample))},
+        "batch_invariance": {"checked": int(len(sample)), "identical": int(same)},
+        "max_abs_err_vs_oracle": err, "oracle_checked": len(small),
+        "status_nonzero": int(np.count_nonzero(ctrl[:, 1])),
+        "layers_ok": bool(np.all(ctrl[:, 0] == [sp.layers for sp in specs])),
+        "tuning": tuning,
+    }
+    print(json.dumps(result))
+
+
+def run_serve(args):
+    """Poisson arrivals of single-image requests (p~U{7..16}, L~U{1..4}, chi~U{2,4,8,16,32});
+    p = 7 requests also run the readout 84 -> 784.  Saturation throughput first (all requests
+    present at t = 0), then traces at 0.5x and 0.9x of it; the same trace through a plain FIFO
+    (one request per call) for comparison."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs, serving
+    prec = anomps.PRECISIONS[args.precision]
+    N = args.requests or 11000
+    warm = min(1000, N // 11)
+    mix = inputs.request_mix(N, list(range(7, 17)), [1, 2, 3, 4], [2, 4, 8, 16, 32], 6)
+    specs = _specs(mix, prec)
+    tuning = _tune(specs, args)
+    m7 = len(inputs.neighbour_pairs(7))
+    ra, rb, rd, rw, rbias = inputs.readout_params(m7, 784, 8)
+    real = torch.float64 if prec == anomps.PREC_FP64 else torch.float32
+    T = lambda v: torch.as_tensor(v, dtype=real, device="cuda").contiguous()
+    coeff = torch.empty((m7, 16), dtype=real, device="cuda")
+    anomps.ano_coeffs(T(ra), T(rb), T(rd), coeff)
+    ro = (coeff, T(rw), T(rbias))
+    free, total = torch.cuda.mem_get_info()
+    arena = int(min(free * 0.5, 64 << 30))
+
+    def make(arrivals, idx):
+        return [serving.Request(k, float(arrivals[j]), specs[k], ro if specs[k].n == 49 else None)
+                for j, k in enumerate(idx)]
+
+    srv = serving.Server(arena)
+    sat_n = min(N, 4000)
+    sat = srv.run(make(np.zeros(sat_n), range(sat_n))).summary()
+    qps_sat = sat["throughput_req_per_s"]
+    runs = {}
+    for frac in (0.5, 0.9):
+        arr = inputs.poisson_arrivals(N, frac * qps_sat, 6)
+        reqs = make(arr, range(N))
+        st = srv.run(reqs)
+        lat = np.array(st.latencies_ms)
+        order = np.argsort([r.arrival for r in reqs])
+        lat_after = np.array([(reqs[i].done_time - reqs[i].arrival) * 1e3 for i in order[warm:]])
+        runs[f"{frac}x"] = {"qps": round(frac * qps_sat, 1), "requests": N, "warmup": warm,
+                            "latency_ms_p50": round(float(np.percentile(lat_after, 50)), 3),
+                            "latency_ms_p99": round(float(np.percentile(lat_after, 99)), 3),
+                            "throughput_req_per_s": round(st.completed / st.wall_s, 1),
+                            "peak_arena_bytes": st.peak_bytes,
+                            "status_nonzero": int(sum(r.status != 0 for r in reqs))}
+        del lat
+    # plain FIFO on the start of the 0.5x trace (bounded: it cannot keep up with that rate)
+    arr = inputs.poisson_arrivals(N, 0.5 * qps_sat, 6)
+    plain_n = min(N, args.plain_images)
+    pst = serving.serve_plain(make(arr, range(plain_n)))
+    # a served request equals the same image run alone
+    check = make(np.zeros(8), range(8))
+    serving.Server(1 << 30).run(check)
+    same = sum(int(np.array_equal(r.features, anomps.extract_features(
+        r.spec.pixels[None], r.spec.theta, r.spec.phi, r.spec.pairs, r.spec.chi,
+        prec)[0].cpu().numpy()[0])) for r in check)
+    result = {
+        "metric": "serving p50/p99 latency and throughput (Poisson arrivals, mixed p/L/chi)",
+        "value": runs["0.9x"]["latency_ms_p99"], "unit": "ms (p99 at 0.9x saturation)",
+        "n_gpus": 1, "higher_is_better": False,
+        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": "single-image requests, p~U{7..16}, L~U{1..4}, "
+                               "chi~U{2,4,8,16,32}, readout 84->784 for p=7",
+                   "requests": N, "arena_bytes": arena},
+        "saturation": sat, "runs": runs,
+        "plain_fifo_0.5x": {**pst.summary(), "requests": plain_n},
+        "batch_invariance": {"checked": len(check), "identical": same},
+        "tuning": tuning,
+    }
+    print(json.dumps(result))
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.workload == "mixed":
+        return run_mixed(args)
+    if args.workload == "serve":
+        return run_serve(args)
     import torch
     from paper_2607_10280_amd import anomps, inputs, workload
 

@@ -71,3 +71,22 @@ def readout_params(m: int, out_dim: int, seed: int, w_std: float = 0.02):
     w = rng.normal(0.0, w_std, size=(out_dim, m))
     bias = np.zeros(out_dim)
     return a, b, d, w, bias
+
+
+def request_mix(count: int, p_choices, layer_choices, chi_choices, seed: int):
+    """Seeded request parameters for mixed batches and serving: for each request (p, L, chi)
+    drawn uniformly from the given choices, plus the seeds of its blob image and its angles.
+    Returns a list of dicts {p, layers, chi, image_seed, angle_seed}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ps = rng.choice(np.asarray(p_choices), size=count)
+    ls = rng.choice(np.asarray(layer_choices), size=count)
+    cs = rng.choice(np.asarray(chi_choices), size=count)
+    base = int(rng.integers(1 << 30))
+    return [{"p": int(ps[i]), "layers": int(ls[i]), "chi": int(cs[i]),
+             "image_seed": base + 2 * i, "angle_seed": base + 2 * i + 1} for i in range(count)]
+
+
+def poisson_arrivals(count: int, qps: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of rate qps: cumulative exponential gaps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))
