@@ -53,9 +53,12 @@ typedef enum {
 
 /* Arithmetic of a batch.  FP64: complex128 state, FP64 everywhere.  FP32: complex64 state,
  * environments, pair contractions and outputs in FP32; the SVD, the orthogonalisation of the
- * canonical sweep and the singular-value renormalisation in FP64.  SPLIT_BF16: as FP32 but the
- * environment and pair contractions use bf16 matrix cores on a hi+lo split of each FP32
- * operand with FP32 accumulation. */
+ * canonical sweep and the singular-value renormalisation in FP64.  SPLIT_BF16: as FP32 but,
+ * for batches whose slot is 16 wide, the environment and pair contractions run on bf16 matrix
+ * cores: each FP32 operand x = x_hi + x_lo (x_hi = bf16(x), x_lo = bf16(x - x_hi)) and each
+ * product a*b = a_hi b_hi + a_hi b_lo + a_lo b_hi, accumulated in FP32 (relative error of a
+ * product term <= ~3 * 2^-18).  Narrower slots use the FP32 vector contractions.  Not accepted
+ * in mixed request tables. */
 typedef enum { MPS_PREC_FP64 = 0, MPS_PREC_FP32 = 1, MPS_PREC_SPLIT_BF16 = 2 } mps_precision;
 
 /* Per-image status word (bit flags, 0 = fine). */

@@ -195,8 +195,6 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
   if (!b->env) return fail(MPS_ERR_INVALID_ARG, "env is NULL");
   if (m < 0) return fail(MPS_ERR_INVALID_ARG, "m=%d < 0", m);
   if (m > 0 && (!pairs || !out)) return fail(MPS_ERR_INVALID_ARG, "pairs/out is NULL");
-  if (b->precision == MPS_PREC_SPLIT_BF16)
-    return fail(MPS_ERR_UNSUPPORTED, "split-bf16 pair contractions are not built in this library");
   const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
   const int L = b->layers_done;
   hipError_t e;
@@ -206,7 +204,7 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
       e = launch_pairs<double, double>((const double*)b->state, (const double*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
   } else if (S == 16) {
     e = launch_measure16((const float*)b->state, (float*)b->env, pairs, m, b->n_sites, b->chi, L,
-                         b->batch, (float*)out, stream);
+                         b->batch, (float*)out, b->precision == MPS_PREC_SPLIT_BF16, stream);
   } else {
     e = launch_envs<float, float>((const float*)b->state, (float*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)

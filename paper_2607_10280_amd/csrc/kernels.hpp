@@ -26,9 +26,11 @@ template <typename T, typename C>
 hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, int n, int chi,
                         int S, int layers, int batch, C* out, hipStream_t stream);
 
-// Matrix-core measurement for 16-wide slots in FP32 (environments + pairs).
+// Matrix-core measurement for 16-wide slots (environments + pairs): FP32 products, or
+// split-BF16 products with FP32 accumulation.
 hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
-                            int chi, int layers, int batch, float* out, hipStream_t stream);
+                            int chi, int layers, int batch, float* out, bool split_bf16,
+                            hipStream_t stream);
 
 // Mixed request tables: entries [begin, begin + count) form one bucket (slot S, precision T).
 template <typename T>

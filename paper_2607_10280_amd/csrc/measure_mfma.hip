@@ -1,6 +1,11 @@
-// Matrix-core versions of the environment sweeps and pair expectations for 16-wide bonds in
-// FP32 (§II-C, Eq. (4)-(5)).  Every contraction is a 16x16x16 complex product, evaluated as
-// real v_mfma_f32_16x16x4f32 products (four per k-chunk: re*re, -im*im, re*im, im*re).
+// Matrix-core versions of the environment sweeps and pair expectations for 16-wide bonds
+// (§II-C, Eq. (4)-(5)).  Every contraction is a 16x16x16 complex product made of four real
+// products (re*re, -im*im, re*im, im*re).  FP32: each real product is four
+// v_mfma_f32_16x16x4f32 (one per k-chunk).  Split-BF16: each FP32 operand x is written as
+// x_hi + x_lo with x_hi = bf16(x) and x_lo = bf16(x - x_hi), and each real product as
+// a_hi b_hi + a_hi b_lo + a_lo b_hi in three v_mfma_f32_16x16x16_bf16 (FP32 accumulation); the
+// dropped a_lo b_lo term and the two roundings leave a relative error of at most ~3 * 2^-18
+// per product term.
 //
 // Operand convention (one wave, lane l, g = l/16): for k-chunk kc the lane supplies
 //   A-operand value  A[l%16][4g+kc],   B-operand value  B[4g+kc][l%16],
@@ -40,14 +45,61 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// C += A B with per-lane operand values for the four k-chunks.
-__device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]) {
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> bf16 bit pattern, round to nearest even (operands here are finite).
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// hi/lo bf16 parts of four FP32 values (the lane's four k entries); `neg` negates both parts.
+struct Split4 {
+  s4 hi, lo;
+};
+__device__ __forceinline__ Split4 split4(float x0, float x1, float x2, float x3, bool neg) {
+  const float x[4] = {x0, x1, x2, x3};
+  const unsigned sg = neg ? 0x8000u : 0u;
+  Split4 r;
 #pragma unroll
-  for (int kc = 0; kc < 4; ++kc) {
-    c.re = mfma(a[kc].re, b[kc].re, c.re);
-    c.re = mfma(-a[kc].im, b[kc].im, c.re);
-    c.im = mfma(a[kc].re, b[kc].im, c.im);
-    c.im = mfma(a[kc].im, b[kc].re, c.im);
+  for (int j = 0; j < 4; ++j) {
+    const unsigned h = bf16_bits(x[j]);
+    const unsigned l = bf16_bits(x[j] - __uint_as_float(h << 16));
+    r.hi[j] = (short)(h ^ sg);
+    r.lo[j] = (short)(l ^ sg);
+  }
+  return r;
+}
+
+__device__ __forceinline__ f4 mfma_split(const Split4& a, const Split4& b, f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
+}
+
+// C += A B with per-lane operand values for the four k-chunks (entry kc of the lane holds
+// k = 4g + kc, which is also the element order of a 16x16x16 bf16 operand).
+template <bool SPLIT>
+__device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]) {
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      c.re = mfma(a[kc].re, b[kc].re, c.re);
+      c.re = mfma(-a[kc].im, b[kc].im, c.re);
+      c.im = mfma(a[kc].re, b[kc].im, c.im);
+      c.im = mfma(a[kc].im, b[kc].re, c.im);
+    }
+  } else {
+    const Split4 ar = split4(a[0].re, a[1].re, a[2].re, a[3].re, false);
+    const Split4 ai = split4(a[0].im, a[1].im, a[2].im, a[3].im, false);
+    const Split4 nai = split4(a[0].im, a[1].im, a[2].im, a[3].im, true);
+    const Split4 br = split4(b[0].re, b[1].re, b[2].re, b[3].re, false);
+    const Split4 bi = split4(b[0].im, b[1].im, b[2].im, b[3].im, false);
+    c.re = mfma_split(ar, br, c.re);
+    c.re = mfma_split(nai, bi, c.re);
+    c.im = mfma_split(ar, bi, c.im);
+    c.im = mfma_split(ai, br, c.im);
   }
 }
 
@@ -113,6 +165,7 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 }
 
 // X_u = E conj(A_u); E' = sum_u A_u^T X_u   (left transfer of one block E held as A-operand)
+template <bool SPLIT>
 __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4], const cf (&a1)[4]) {
   Acc out = acc_zero();
   cf ac[4], xb[4];
@@ -122,9 +175,9 @@ __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4]
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{au[kc].re, -au[kc].im};
     Acc x = acc_zero();
-    cgemm(x, e, ac);
+    cgemm<SPLIT>(x, e, ac);
     acc_as_b(x, xb);
-    cgemm(out, au, xb);
+    cgemm<SPLIT>(out, au, xb);
   }
   return out;
 }
@@ -133,6 +186,7 @@ __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4]
 
 // ------------------------------------------------------------------------- environments
 // One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).
+template <bool SPLIT>
 __device__ __forceinline__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
   __shared__ cf at[2 * 16 * TS];
   __shared__ cf E[16 * TS];
@@ -163,7 +217,7 @@ __device__ __forceinline__ void env16_image(const float* st, float* ev, int n, i
       ld_rowop(E, e, false);
       ld_colop(at, a0, false);
       ld_colop(at + 16 * TS, a1, false);
-      const Acc out = left_transfer(e, a0, a1);
+      const Acc out = left_transfer<SPLIT>(e, a0, a1);
       __syncthreads();
       st_acc(E, out);
       __syncthreads();
@@ -184,10 +238,10 @@ __device__ __forceinline__ void env16_image(const float* st, float* ev, int n, i
       for (int s = 0; s < 2; ++s) {
         ld_rowop(at + s * 16 * TS, ah, true);   // B-operand of R A_s^H: conj(A_s[l%16][4g+kc])
         Acc y = acc_zero();
-        cgemm(y, r, ah);
+        cgemm<SPLIT>(y, r, ah);
         acc_as_b(y, yb);
         ld_rowop(at + s * 16 * TS, as_, false);  // A-operand A_s[l%16][4g+kc]
-        cgemm(out, as_, yb);
+        cgemm<SPLIT>(out, as_, yb);
       }
       __syncthreads();
       st_acc(E, out);
@@ -210,6 +264,7 @@ __device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
 
 // One image and one start site i: st = its n slots, evL = its environments ([2][n+1][16][16]),
 // out = its [m][15] outputs.
+template <bool SPLIT>
 __device__ __forceinline__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
                               int chi, int layers, int i, float* out) {
   __shared__ cf F[3][16 * TS];
@@ -283,17 +338,17 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
     Acc x = acc_zero();
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{a0[kc].re, -a0[kc].im};
-    cgemm(x, lo, ac);
+    cgemm<SPLIT>(x, lo, ac);
     acc_as_b(x, x0);
     x = acc_zero();
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{a1[kc].re, -a1[kc].im};
-    cgemm(x, lo, ac);
+    cgemm<SPLIT>(x, lo, ac);
     acc_as_b(x, x1);
     Acc f00 = acc_zero(), f01 = acc_zero(), f11 = acc_zero();
-    cgemm(f00, a0, x0);
-    cgemm(f01, a0, x1);
-    cgemm(f11, a1, x1);
+    cgemm<SPLIT>(f00, a0, x0);
+    cgemm<SPLIT>(f01, a0, x1);
+    cgemm<SPLIT>(f11, a1, x1);
     st_acc(F[0], f00);
     st_acc(F[1], f01);
     st_acc(F[2], f11);
@@ -312,7 +367,7 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
 #pragma unroll
       for (int blk = 0; blk < 3; ++blk) {
         ld_rowop(F[blk], e, false);
-        nf[blk] = left_transfer(e, a0, a1);
+        nf[blk] = left_transfer<SPLIT>(e, a0, a1);
       }
       __syncthreads();
 #pragma unroll
@@ -329,20 +384,20 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
       ld_rowop(Ev, r, false);
       ld_rowop(at, ah, true);
       Acc y = acc_zero();
-      cgemm(y, r, ah);
+      cgemm<SPLIT>(y, r, ah);
       acc_as_b(y, y0);
       ld_rowop(at + 16 * TS, ah, true);
       y = acc_zero();
-      cgemm(y, r, ah);
+      cgemm<SPLIT>(y, r, ah);
       acc_as_b(y, y1);
       G[0] = acc_zero();
       G[1] = acc_zero();
       G[2] = acc_zero();
       ld_rowop(at, as_, false);
-      cgemm(G[0], as_, y0);
-      cgemm(G[1], as_, y1);
+      cgemm<SPLIT>(G[0], as_, y0);
+      cgemm<SPLIT>(G[1], as_, y1);
       ld_rowop(at + 16 * TS, as_, false);
-      cgemm(G[2], as_, y1);
+      cgemm<SPLIT>(G[2], as_, y1);
     }
     // rho[(s,t),(s',t')] = sum_{d,d'} F^{ss'}[d][d'] G^{tt'}[d][d'];  entry e = ((s*2+t)*2+s')*2+t'
     float part[32];
@@ -406,6 +461,7 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
 
 // Workgroup w runs on XCD w % 8; all workgroups of one image sit on the same XCD so that its
 // state and environments are shared through that XCD's L2.
+template <bool SPLIT>
 __global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int n, int chi,
                                               int layers, int batch) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
@@ -413,10 +469,11 @@ __global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int
   const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
   const int b = NXCD * (j >> 1) + xcd, side = j & 1;
   if (b >= batch) return;
-  env16_image(state + (size_t)b * n * SLOT, env + ((size_t)b * 2 + side) * (n + 1) * ETILE, n, chi,
+  env16_image<SPLIT>(state + (size_t)b * n * SLOT, env + ((size_t)b * 2 + side) * (n + 1) * ETILE, n, chi,
               layers, side);
 }
 
+template <bool SPLIT>
 __global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* env,
                                                 const int* pairs, int m, int n, int chi,
                                                 int layers, int batch, float* out) {
@@ -425,7 +482,7 @@ __global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* 
   const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
   const int b = NXCD * (jw / (n - 1)) + xcd, i = jw % (n - 1);
   if (b >= batch) return;
-  pairs16_image(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs, m, n,
+  pairs16_image<SPLIT>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs, m, n,
                 chi, layers, i, out + (size_t)b * m * 15);
 }
 
@@ -437,7 +494,7 @@ __global__ __launch_bounds__(W) void k_env16_mixed(const mps_request* reqs, int 
   if (r >= count) return;
   const mps_request* q = reqs + begin + r;
   const int n = uniform_int(q->n_sites), layers = uniform_int(uniform_ptr(q->ctrl)[0]);
-  env16_image(uniform_ptr((const float*)q->state),
+  env16_image<false>(uniform_ptr((const float*)q->state),
               uniform_ptr((float*)q->env) + (size_t)side * (n + 1) * ETILE, n, uniform_int(q->chi),
               layers, side);
 }
@@ -451,7 +508,7 @@ __global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, in
   const int n = uniform_int(q->n_sites), m = uniform_int(q->n_pairs);
   if (i >= n - 1 || m == 0) return;
   const int layers = uniform_int(uniform_ptr(q->ctrl)[0]);
-  pairs16_image(uniform_ptr((const float*)q->state), uniform_ptr((const float*)q->env),
+  pairs16_image<false>(uniform_ptr((const float*)q->state), uniform_ptr((const float*)q->env),
                 uniform_ptr(q->pairs), m, n, uniform_int(q->chi), layers, i,
                 uniform_ptr((float*)q->out));
 }
@@ -467,16 +524,25 @@ hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count,
   return hipGetLastError();
 }
 
-hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
-                            int chi, int layers, int batch, float* out, hipStream_t stream) {
+template <bool SPLIT>
+static hipError_t launch_measure16_t(const float* state, float* env, const int* pairs, int m, int n,
+                                     int chi, int layers, int batch, float* out, hipStream_t stream) {
   const int groups = (batch + NXCD - 1) / NXCD;
-  hipLaunchKernelGGL(k_env16, dim3((unsigned)(NXCD * groups * 2)), dim3(W), 0, stream, state,
-                     env, n, chi, layers, batch);
+  hipLaunchKernelGGL((k_env16<SPLIT>), dim3((unsigned)(NXCD * groups * 2)), dim3(W), 0, stream,
+                     state, env, n, chi, layers, batch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || m == 0) return e;
-  hipLaunchKernelGGL(k_pairs16, dim3((unsigned)((size_t)NXCD * groups * (n - 1))), dim3(W), 0,
-                     stream, state, (const float*)env, pairs, m, n, chi, layers, batch, out);
+  hipLaunchKernelGGL((k_pairs16<SPLIT>), dim3((unsigned)((size_t)NXCD * groups * (n - 1))), dim3(W),
+                     0, stream, state, (const float*)env, pairs, m, n, chi, layers, batch, out);
   return hipGetLastError();
+}
+
+hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
+                            int chi, int layers, int batch, float* out, bool split_bf16,
+                            hipStream_t stream) {
+  return split_bf16
+      ? launch_measure16_t<true>(state, env, pairs, m, n, chi, layers, batch, out, stream)
+      : launch_measure16_t<false>(state, env, pairs, m, n, chi, layers, batch, out, stream);
 }
 
 }  // namespace anomps

@@ -240,3 +240,27 @@ def test_headline_size_sampled(A):
     sample = [0, 1, 511, 1023]
     ref = ofeat.exact_features(x[sample], th, ph, pairs)
     assert np.abs(out[sample] - ref).max() <= FP32_TOL
+
+
+# ------------------------------------------------------------------ split-BF16 contractions
+# Each product term carries a relative error of at most ~3 * 2^-18 (two bf16 roundings and the
+# dropped lo*lo term); an expectation passes through about 2n + 2p such contraction levels
+# (environment sweep and pair transfers), which gives ~1e-3 for 7x7 and ~4e-3 for 16x16 if
+# every level erred at the bound in the same direction.  The test bar is that linear bound.
+SPLIT_TOL = {7: 2.0 ** -10, 16: 2.0 ** -8}
+
+
+@pytest.mark.parametrize("p", [7, 16])
+def test_split_bf16_contractions(A, p):
+    n, B, L = p * p, 2, 4
+    x = inputs.blob_images(B, p, 150 + p)
+    th, ph = inputs.layer_angles(L, n, 151 + p)
+    pairs = inputs.neighbour_pairs(p)
+    out, st = run(A, x, th, ph, pairs, 16, A.PREC_SPLIT_BF16)
+    f32, _ = run(A, x, th, ph, pairs, 16, A.PREC_FP32)
+    assert np.all(st == 0) and out.dtype == np.float32
+    ref = ofeat.exact_features(x, th, ph, pairs)
+    err, err32 = np.abs(out - ref).max(), np.abs(f32 - ref).max()
+    print(f"[split-bf16] p={p} max err {err:.3e} (fp32 {err32:.3e})", flush=True)
+    assert err <= SPLIT_TOL[p]
+    assert err > 0  # the variant really runs (a bit-exact match would mean the FP32 path ran)
