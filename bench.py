@@ -59,11 +59,12 @@ def parse():
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--chi", type=int, default=16)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_bf16"])
     ap.add_argument("--plain-images", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "mixed", "serve"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "mixed", "serve", "grid"],
                     help="headline: the 7x7 L=4 chi=16 batch; mixed: 4096 requests of mixed size "
                          "and depth through the persistent mixed-table launches; serve: Poisson "
                          "arrivals through the continuous-batching loop")
@@ -276,6 +277,66 @@ def run_serve(args):
     print(json.dumps(result))
 
 
+def run_grid(args):
+    """The 7x7 grid of depths and bond limits at batch 1024: images/s per (L, chi) cell and the
+    max error of sampled images against the oracle (exact where chi >= 2^L, the truncated
+    oracle otherwise)."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs
+    from oracle import features as ofeat
+    prec = anomps.PRECISIONS[args.precision]
+    p, B = args.p, args.batch
+    n = p * p
+    x = inputs.blob_images(B, p, 2)
+    pairs = inputs.neighbour_pairs(p)
+    pd = torch.as_tensor(pairs, device="cuda")
+    pix = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    real = torch.float64 if prec == anomps.PREC_FP64 else torch.float32
+    cells = []
+    for L in (1, 2, 3, 4):
+        th, ph = inputs.layer_angles(L, n, 3 + L)
+        thd = torch.as_tensor(th, device="cuda").contiguous()
+        phd = torch.as_tensor(ph, device="cuda").contiguous()
+        for chi in (2, 4, 8, 16):
+            b = anomps.new_batch(n, chi, L, B, prec)
+            out = torch.empty((B, len(pairs), 15), dtype=real, device="cuda")
+
+            def step():
+                anomps.init_batch(b, pix)
+                for layer in range(L):
+                    anomps.apply_layer(b, thd[layer], phd[layer])
+                anomps.pauli_pair_expect(b, pd, out)
+            step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            o = out.cpu().numpy()
+            sample = [0, B // 2, B - 1]
+            if chi >= 2 ** L:
+                ref = ofeat.exact_features(x[sample], th, ph, pairs)
+                kind = "exact"
+            else:
+                ref = ofeat.truncated_features(x[sample], th, ph, pairs, chi)[0]
+                kind = "truncated"
+            cells.append({"L": L, "chi": chi, "images_per_s": round(B / (ms * 1e-3), 1),
+                          "ms": round(ms, 4), "max_abs_err": float(np.abs(o[sample] - ref).max()),
+                          "oracle": kind, "status_nonzero": int(np.count_nonzero(b.status.cpu()))})
+            del b, out
+    head = next(c for c in cells if c["L"] == 4 and c["chi"] == 16)
+    print(json.dumps({
+        "metric": "Pauli-feature images/sec per (L, chi) cell, 7x7, batch 1024",
+        "value": head["images_per_s"], "unit": "images/s (L=4, chi=16 cell)", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": True, "data": "synthetic",
+        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision,
+        "config": {"workload": f"{p}x{p} Gaussian blobs, L in 1..4 x chi in {{2,4,8,16}}",
+                   "global_batch": B}, "cells": cells}))
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     args = parse()
@@ -286,6 +347,8 @@ def main():
         return run_mixed(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "grid":
+        return run_grid(args)
     import torch
     from paper_2607_10280_amd import anomps, inputs, workload
 
@@ -418,7 +481,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else "f64",
+        "dtype": {anomps.PREC_FP32: "c64+f64svd", anomps.PREC_FP64: "f64",
+                  anomps.PREC_SPLIT_BF16: "c64(split-bf16 mfma)+f64svd"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{p}x{p} images ({n} qubits), Gaussian blobs, L={L}, chi={chi}, "
                                f"{m} H+V pairs x 15 Paulis, readout {m}->{out_dim}",
