@@ -52,12 +52,19 @@ def layer_angles(n_layers: int, n: int, seed: int) -> tuple[np.ndarray, np.ndarr
     return theta, phi
 
 
-def neighbour_pairs(p: int) -> np.ndarray:
+def neighbour_pairs(p: int, diagonal: bool = False) -> np.ndarray:
     """Image-local pairs of a p x p grid (§II-C): horizontal pairs (k, k+1) in row-major
-    order of k, then vertical pairs (k, k+p) in row-major order.  int32 [2p(p-1)][2]."""
+    order of k, then vertical pairs (k, k+p) in row-major order; int32 [2p(p-1)][2].  With
+    `diagonal`, also the diagonal neighbours (r,c)-(r+1,c+1) and then the anti-diagonal ones
+    (r,c+1)-(r+1,c), each row-major: 2p(p-1) + 2(p-1)^2 pairs (156 at p = 7, the paper's
+    count)."""
     h = [(r * p + c, r * p + c + 1) for r in range(p) for c in range(p - 1)]
     v = [(r * p + c, (r + 1) * p + c) for r in range(p - 1) for c in range(p)]
-    return np.asarray(h + v, dtype=np.int32).reshape(-1, 2)
+    d = a = []
+    if diagonal:
+        d = [(r * p + c, (r + 1) * p + c + 1) for r in range(p - 1) for c in range(p - 1)]
+        a = [(r * p + c + 1, (r + 1) * p + c) for r in range(p - 1) for c in range(p - 1)]
+    return np.asarray(h + v + d + a, dtype=np.int32).reshape(-1, 2)
 
 
 def readout_params(m: int, out_dim: int, seed: int, w_std: float = 0.02):
