@@ -136,6 +136,35 @@ int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream);
 int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
                     hipStream_t stream);
 
+/* Layer programs of mps_apply_layer_program. */
+enum {
+  MPS_LAYER_RYRZ_LADDER = 0,    /* R_Y(theta_k) R_Z(phi_k), then the CNOT ladder (mps_apply_layer) */
+  MPS_LAYER_H_RY_BRICKWORK = 1  /* the paper's encoding-entangling layer, see below */
+};
+
+/*
+ * Apply the next layer of a given program.
+ *  MPS_LAYER_RYRZ_LADDER: exactly mps_apply_layer (pixels ignored, may be NULL).
+ *  MPS_LAYER_H_RY_BRICKWORK (§II-B, Eq. (2)): on every qubit a Hadamard gate followed by
+ *    R_Y(phi_k), phi_k = 2 pi x_k - pi from the image's own pixel, then CNOT(k, k+1) on every
+ *    even bond k, then on every odd bond (staggered nearest-neighbour CNOTs).  Implemented as a
+ *    right-canonical sweep (gates applied), a left-to-right sweep over the even bonds, a second
+ *    right-canonical sweep and a sweep over the odd bonds; bonds without a CNOT in a sweep only
+ *    move the orthogonality centre.  Bond dimensions after the layer follow mps_bond_dim; start
+ *    the batch from |0...0> with mps_init_zero.  pixels: device [batch][n_sites] float64
+ *    (theta, phi ignored, may be NULL).
+ *  trunc_err as in mps_apply_layer (each bond once per layer).
+ * Errors: MPS_ERR_INVALID_ARG for an unknown program or a NULL argument it needs, and as
+ * mps_apply_layer.
+ */
+int mps_apply_layer_program(mps_batch* b, int32_t program, const double* theta,
+                            const double* phi, const double* pixels, double* trunc_err,
+                            hipStream_t stream);
+
+/* Product state |0...0> for every image (the start of the paper's encoding circuit); clears
+ * status and sets layers_done = 0. */
+int mps_init_zero(mps_batch* b, hipStream_t stream);
+
 /*
  * Host-side check of a pair list (host pointer): 0 <= i < j < n_sites for every pair.
  * Returns MPS_OK or MPS_ERR_INVALID_ARG (with the first offending pair in mps_last_error()).

@@ -99,7 +99,7 @@ def _canonicalise(m: mps_mod.MPS, site_gates) -> None:
         a[0] = np.einsum("st,ltr->lsr", site_gates[0], a[0])
 
 
-def _sweep(m: mps_mod.MPS, chi, parity: int, errs: np.ndarray) -> None:
+def _sweep(m: mps_mod.MPS, chi, parity: int, errs: np.ndarray, gaps: np.ndarray) -> None:
     """Left-to-right two-site sweep: CNOT on bonds k with k % 2 == parity, a pure centre move
     elsewhere."""
     a = m.tensors
@@ -120,6 +120,7 @@ def _sweep(m: mps_mod.MPS, chi, parity: int, errs: np.ndarray) -> None:
         total = float(np.sum(s * s))
         if gate:
             errs[k] = float(np.sum(s[d:] ** 2)) / total
+            gaps[k] = s[d - 1] - s[d] if d < len(s) else np.inf
         kept = s[:d] / np.linalg.norm(s[:d])
         a[k] = u[:, :d].reshape(dl, 2, d)
         a[k + 1] = (kept[:, None] * vh[:d]).reshape(d, 2, dr)
@@ -131,12 +132,13 @@ def mps_simulate(x, layers: int, chi=None) -> mps_mod.MPS:
     m = mps_mod.MPS([np.array([1.0, 0.0], dtype=np.complex128).reshape(1, 2, 1) for _ in range(n)])
     site_gates = [gates.ry(p) @ H for p in angle(x)]
     for _ in range(layers):
-        errs = np.zeros(n - 1)
+        errs, gaps = np.zeros(n - 1), np.full(n - 1, np.inf)
         _canonicalise(m, site_gates)
-        _sweep(m, chi, 0, errs)
+        _sweep(m, chi, 0, errs, gaps)
         _canonicalise(m, None)
-        _sweep(m, chi, 1, errs)
+        _sweep(m, chi, 1, errs, gaps)
         m.trunc_err.append(errs)
+        m.gaps.append(gaps)
     return m
 
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libanomps.so")
 MPS_OK = 0
 PREC_FP64, PREC_FP32, PREC_SPLIT_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16}
+LAYER_RYRZ_LADDER, LAYER_H_RY_BRICKWORK = 0, 1
 IMG_NONFINITE, IMG_NO_CONVERGENCE = 1, 2
 MAX_BOND = 16
 
@@ -85,6 +86,10 @@ EXPORTS = {
     "mps_init_batch": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p]),
     "mps_apply_layer": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_apply_layer_program": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_init_zero": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p]),
     "mps_validate_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mps_pauli_pair_expect": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p,
                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -205,6 +210,16 @@ def apply_layer(b: Batch, theta, phi, trunc_err=None, stream=None) -> None:
                                  _stream(stream)))
 
 
+def apply_layer_program(b: Batch, program: int, theta=None, phi=None, pixels=None,
+                        trunc_err=None, stream=None) -> None:
+    _check(lib().mps_apply_layer_program(ctypes.byref(b.desc), program, _ptr(theta), _ptr(phi),
+                                         _ptr(pixels), _ptr(trunc_err), _stream(stream)))
+
+
+def init_zero(b: Batch, stream=None) -> None:
+    _check(lib().mps_init_zero(ctypes.byref(b.desc), _stream(stream)))
+
+
 def pauli_pair_expect(b: Batch, pairs_dev, out, stream=None) -> None:
     m = 0 if pairs_dev is None else pairs_dev.shape[0]
     _check(lib().mps_pauli_pair_expect(ctypes.byref(b.desc), _ptr(pairs_dev), m, _ptr(out),
@@ -247,6 +262,33 @@ def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_
     for layer in range(L):
         tl = torch.empty((B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
         apply_layer(b, th[layer], ph[layer], tl, stream)
+        if return_trunc_err:
+            te[:, layer] = tl
+    pd = torch.as_tensor(pairs_np, device=dev)
+    out = torch.empty((B, len(pairs_np), 15), dtype=b.real_dtype, device=dev)
+    pauli_pair_expect(b, pd, out, stream)
+    if return_trunc_err:
+        return out, b.status, te
+    return out, b.status
+
+
+def paper_features(pixels, layers: int, pairs, chi: int, precision: int = PREC_FP32,
+                   stream=None, return_trunc_err: bool = False):
+    """The paper's own encoding circuit (§II-B, Eq. (2)) for a batch: |0...0>, then `layers`
+    layers of H, R_Y(2 pi x - pi) and brickwork CNOTs, then the Pauli-pair expectations.
+    pixels [B][n]; returns device tensors (features [B][m][15], status [B][, trunc_err])."""
+    import torch
+    dev = torch.device("cuda")
+    pairs_np = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    pix = torch.as_tensor(pixels, dtype=torch.float64, device=dev).contiguous()
+    B, n = pix.shape
+    validate_pairs(pairs_np, n)
+    b = new_batch(n, chi, layers, B, precision)
+    init_zero(b, stream)
+    te = torch.zeros((B, max(layers, 1), n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+    for layer in range(layers):
+        tl = torch.empty((B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+        apply_layer_program(b, LAYER_H_RY_BRICKWORK, None, None, pix, tl, stream)
         if return_trunc_err:
             te[:, layer] = tl
     pd = torch.as_tensor(pairs_np, device=dev)

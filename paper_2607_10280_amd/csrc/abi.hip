@@ -153,23 +153,49 @@ int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream) {
   return ok();
 }
 
-int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
-                    hipStream_t stream) {
+int mps_apply_layer_program(mps_batch* b, int32_t program, const double* theta,
+                            const double* phi, const double* pixels, double* trunc_err,
+                            hipStream_t stream) {
   int rc = check_batch(b);
   if (rc) return rc;
-  if (!theta || !phi) return fail(MPS_ERR_INVALID_ARG, "theta/phi is NULL");
+  if (program == MPS_LAYER_RYRZ_LADDER) {
+    if (!theta || !phi) return fail(MPS_ERR_INVALID_ARG, "theta/phi is NULL");
+  } else if (program == MPS_LAYER_H_RY_BRICKWORK) {
+    if (!pixels) return fail(MPS_ERR_INVALID_ARG, "pixels is NULL");
+  } else {
+    return fail(MPS_ERR_INVALID_ARG, "layer program %d unknown", program);
+  }
   if (b->layers_done < 0 || b->layers_done >= b->n_layers)
     return fail(MPS_ERR_INVALID_ARG, "layers_done=%d: batch sized for %d layers", b->layers_done, b->n_layers);
   const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
   hipError_t e;
   if (b->precision == MPS_PREC_FP64)
     e = launch_layer<double>((double*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
-                             theta, phi, trunc_err, b->status, stream);
+                             program, theta, phi, pixels, trunc_err, b->status, stream);
   else
     e = launch_layer<float>((float*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
-                            theta, phi, trunc_err, b->status, stream);
+                            program, theta, phi, pixels, trunc_err, b->status, stream);
   if (e != hipSuccess) return check_hip(e, "layer launch");
   b->layers_done += 1;
+  return ok();
+}
+
+int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
+                    hipStream_t stream) {
+  return mps_apply_layer_program(b, MPS_LAYER_RYRZ_LADDER, theta, phi, nullptr, trunc_err, stream);
+}
+
+int mps_init_zero(mps_batch* b, hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
+  hipError_t e;
+  if (b->precision == MPS_PREC_FP64)
+    e = launch_encode<double>((double*)b->state, nullptr, b->n_sites, S, b->batch, b->status, stream);
+  else
+    e = launch_encode<float>((float*)b->state, nullptr, b->n_sites, S, b->batch, b->status, stream);
+  if (e != hipSuccess) return check_hip(e, "encode launch");
+  b->layers_done = 0;
   return ok();
 }
 

@@ -11,10 +11,12 @@ template <typename T>
 hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch, int* status,
                          hipStream_t stream);
 
+// program 0: R_Y R_Z gates + CNOT ladder (theta, phi); program 1: the paper's H, R_Y(2 pi x - pi)
+// gates from pixels + brickwork CNOTs.
 template <typename T>
-hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch,
-                        const double* theta, const double* phi, double* trunc_err, int* status,
-                        hipStream_t stream);
+hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, int program,
+                        const double* theta, const double* phi, const double* pixels,
+                        double* trunc_err, int* status, hipStream_t stream);
 
 // Environment sweeps (left and right) and pair expectations.  T = storage type of the state,
 // C = compute/output type of the measurement (double for FP64 batches, float otherwise).

@@ -22,14 +22,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------------------------- encode
-// One workgroup per image: writes A[k] = (cos(pi x_k/2), sin(pi x_k/2)) as a 1x2x1 tensor and
-// (re)sets the image's status word (NaN/Inf pixels -> non-finite).
+// One workgroup per image: writes A[k] = (cos(pi x_k/2), sin(pi x_k/2)) as a 1x2x1 tensor (|0>
+// for every site when pixels is null) and (re)sets the image's status word (NaN/Inf pixels ->
+// non-finite).
 template <typename T>
 __global__ void k_encode(T* state, const double* pixels, int n, int S, int* status) {
   const int b = blockIdx.x;
   int bad = 0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double x = pixels[(size_t)b * n + k];
+    const double x = pixels ? pixels[(size_t)b * n + k] : 0.0;  // no pixels: |0>
     double s, c;
     sincos(0.5 * M_PI * x, &s, &c);
     T* slot = state + ((size_t)b * n + k) * (size_t)(2 * S * S) * 2;
@@ -251,24 +252,50 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   return kImgNoConvergence;  // unreachable for shapes within the slot
 }
 
-// Apply U = R_Y(theta) R_Z(phi) to the physical index of the (Dl x 2 x Dr) tensor in ta.
+// One-qubit gates of a layer program, per site k.
+enum : int { kGateNone = 0, kGateRyRz = 1, kGateHRy = 2 };
+struct Gate2 {
+  cd u00, u01, u10, u11;
+};
+// kGateRyRz: U = R_Y(theta_k) R_Z(phi_k).  kGateHRy: U = R_Y(2 pi x_k - pi) H (§II-B, Eq. (2):
+// Hadamard first, then the pixel rotation), i.e. (1/sqrt 2)[[c-s, c+s], [s+c, s-c]] with
+// c = cos(phi/2), s = sin(phi/2).
+__device__ __forceinline__ Gate2 site_gate(int mode, int k, const double* theta,
+                                           const double* phi, const double* pix) {
+  Gate2 g;
+  if (mode == kGateHRy) {
+    double s, c;
+    sincos(0.5 * (2.0 * M_PI * pix[k] - M_PI), &s, &c);
+    const double r = 0.70710678118654752440;
+    g.u00 = cd{(c - s) * r, 0.0};
+    g.u01 = cd{(c + s) * r, 0.0};
+    g.u10 = cd{(s + c) * r, 0.0};
+    g.u11 = cd{(s - c) * r, 0.0};
+  } else {
+    double st, ct, sp, cp;
+    sincos(0.5 * theta[k], &st, &ct);
+    sincos(0.5 * phi[k], &sp, &cp);
+    const cd em{cp, -sp}, ep{cp, sp};  // e^{-i phi/2}, e^{+i phi/2}
+    g.u00 = cscale(em, ct);
+    g.u01 = cscale(ep, -st);
+    g.u10 = cscale(em, st);
+    g.u11 = cscale(ep, ct);
+  }
+  return g;
+}
+
+// Apply a one-qubit gate to the physical index of the (Dl x 2 x Dr) tensor in ta.
 template <int S, typename T>
-__device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, double theta, double phi) {
+__device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, const Gate2& g) {
   constexpr int SP = LayerShared<S, T>::SP;
-  double st, ct, sp, cp;
-  sincos(0.5 * theta, &st, &ct);
-  sincos(0.5 * phi, &sp, &cp);
-  const cd em{cp, -sp}, ep{cp, sp};  // e^{-i phi/2}, e^{+i phi/2}
-  const cd u00 = cscale(em, ct), u01 = cscale(ep, -st);
-  const cd u10 = cscale(em, st), u11 = cscale(ep, ct);
   const FastDiv fd(Dr);
   for (int idx = threadIdx.x; idx < Dl * Dr; idx += kLayerThreads) {
     const int a = fd.q(idx), b = fd.r(idx);
     const cd v0 = sh.ta[(a * 2 + 0) * SP + b];
     const cd v1 = sh.ta[(a * 2 + 1) * SP + b];
-    cd w0 = cmul(u00, v0), w1 = cmul(u10, v0);
-    cfma(w0, u01, v1);
-    cfma(w1, u11, v1);
+    cd w0 = cmul(g.u00, v0), w1 = cmul(g.u10, v0);
+    cfma(w0, g.u01, v1);
+    cfma(w1, g.u11, v1);
     sh.ta[(a * 2 + 0) * SP + b] = w0;
     sh.ta[(a * 2 + 1) * SP + b] = w1;
   }
@@ -321,30 +348,30 @@ __device__ __forceinline__ cd to_cd(cx<T> v) {
   return cd{(double)v.re, (double)v.im};
 }
 
-// Applies layer `layer` (0-based) to one image whose n slots start at `st`.
-template <int S, typename T>
-__device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
-                            const double* theta, const double* phi, double* trunc_err,
-                            int* status) {
+// Right-to-left sweep: apply the one-qubit gates (mode != kGateNone) and bring sites n-1..1
+// to right-canonical form; the centre ends in ta as site 0.  dims(k) = bond k's dimension.
+// With from_lds the tensor of site n-1 is already in ta (the end of a preceding CNOT sweep).
+template <int S, typename T, typename Dims>
+__device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, Dims dims, int mode,
+                                           const double* theta, const double* phi,
+                                           const double* pix, bool from_lds,
+                                           SitePrefetch<S, T>& pf) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
   constexpr size_t SLOT = (size_t)2 * S * S * 2;  // T values per site slot
   const int tid = threadIdx.x;
   int flags = 0;
-  auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
-  auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
-  SitePrefetch<S, T> pf;
-
-  // ---- right-to-left sweep: gate every site, make sites n-1..1 right-canonical.
-  pf.load(st + (size_t)(n - 1) * SLOT, dold(n - 2), 1);
-  pf.commit(sh.tb);
-  __syncthreads();
-  for (int idx = tid; idx < dold(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * SP] = to_cd(sh.tb[idx * SP]);
-  __syncthreads();
+  if (!from_lds) {
+    pf.load(st + (size_t)(n - 1) * SLOT, dims(n - 2), 1);
+    pf.commit(sh.tb);
+    __syncthreads();
+    for (int idx = tid; idx < dims(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * SP] = to_cd(sh.tb[idx * SP]);
+    __syncthreads();
+  }
   for (int k = n - 1; k >= 1; --k) {
-    const int Dl = dold(k - 1), Dr = dold(k), Dll = dold(k - 2);
+    const int Dl = dims(k - 1), Dr = dims(k), Dll = dims(k - 2);
     pf.load(st + (size_t)(k - 1) * SLOT, Dll, Dl);
-    apply_gate<S, T>(sh, Dl, Dr, theta[k], phi[k]);
+    if (mode != kGateNone) apply_gate<S, T>(sh, Dl, Dr, site_gate(mode, k, theta, phi, pix));
     // mat = t^H: rows (s, b) -> s*Dr + b, columns a; rows [M, MP) zero.
     const int M = 2 * Dr, N = Dl;
     const int MP = jacobi_shape(M, N).MP;
@@ -393,18 +420,34 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     }
     __syncthreads();
   }
-  apply_gate<S, T>(sh, 1, dold(0), theta[0], phi[0]);
+  if (mode != kGateNone) apply_gate<S, T>(sh, 1, dims(0), site_gate(mode, 0, theta, phi, pix));
+  return flags;
+}
 
-  // ---- left-to-right CNOT ladder with SVD truncation.
-  pf.load(st + (size_t)1 * SLOT, dold(0), dold(1));
+// Left-to-right two-site sweep starting from the centre (site 0) in ta.  Bond k gets a CNOT
+// (control k) when parity < 0 or k % 2 == parity, else the update only moves the centre.
+// before(k)/after(k) = bond dimensions before/after this sweep; bond k keeps after(k) singular
+// triplets (for a CNOT bond min(chi, rows, cols, 2 before(k)), for a plain move before(k)).
+// trunc_err[k] receives the discarded weight of every CNOT bond.
+template <int S, typename T, typename Before, typename After>
+__device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, Before before,
+                                          After after, int parity, double* trunc_err,
+                                          SitePrefetch<S, T>& pf) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  const int tid = threadIdx.x;
+  int flags = 0;
+  pf.load(st + (size_t)1 * SLOT, before(0), before(1));
   for (int k = 0; k <= n - 2; ++k) {
-    const int Dl = dnew(k - 1), Dc = dold(k), Dr = dold(k + 1);
+    const int Dl = after(k - 1), Dc = before(k), Dr = before(k + 1), D = after(k);
+    const int cx = (parity < 0 || (k & 1) == parity) ? 1 : 0;
     pf.commit(sh.tb);
     __syncthreads();
-    if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, dold(k + 1), dold(k + 2));
+    if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
     const int M = 2 * Dl, N = 2 * Dr;
     const int MP = jacobi_shape(M, N).MP;
-    // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR s, b]   (CNOT control k).
+    // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR (cx s), b]   (CNOT control k).
     {
       const FastDiv fmp(MP), fdr(Dr);
       for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
@@ -413,14 +456,13 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
         cd acc{0.0, 0.0};
         if (row < M)
           for (int c = 0; c < Dc; ++c)
-            cfma(acc, sh.ta[row * SP + c], to_cd(sh.tb[(c * 2 + (t ^ s_)) * SP + b]));
+            cfma(acc, sh.ta[row * SP + c], to_cd(sh.tb[(c * 2 + (t ^ (s_ & cx))) * SP + b]));
         sh.mat[col * LD + row] = acc;
       }
     }
     __syncthreads();
     flags |= jacobi_columns<S, T>(sh, M, N);
     const double tiny2 = sh.tiny2;
-    const int D = min(chi, min(M, N));
     // Rank columns by singular value (descending, ties by index; NaN counts as zero); thread c
     // owns column c (N <= 2S <= 64).
     if (tid < N) {
@@ -443,7 +485,7 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     }
     if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
     const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
-    if (tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
+    if (cx && tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
     // U columns = normalised kept columns of W (numerically zero columns become zero).
     {
       const FastDiv fd(D);
@@ -480,25 +522,58 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
         cd acc{0.0, 0.0};
         for (int c = 0; c < Dc; ++c) {
           cfma(acc, sh.mat[j * SP + c], to_cd(sh.tb[(c * 2 + t) * SP + b]));
-          cfma(acc, sh.mat[(S + j) * SP + c], to_cd(sh.tb[(c * 2 + (t ^ 1)) * SP + b]));
+          cfma(acc, sh.mat[(S + j) * SP + c], to_cd(sh.tb[(c * 2 + (t ^ cx)) * SP + b]));
         }
         sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
       }
     }
     __syncthreads();
   }
-  store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, dnew(n - 2), 1);
-  if (tid == 0 && flags) status[0] |= flags;
+  store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, after(n - 2), 1);
+  return flags;
 }
 
+// Applies layer `layer` (0-based) to one image whose n slots start at `st`.
+//  program kLayerRyRzLadder: R_Y(theta_k) R_Z(phi_k) on every site, then CNOT(k, k+1) for
+//    k = 0..n-2 in order: one canonical sweep and one CNOT sweep.
+//  program kLayerHRyBrickwork (§II-B, Eq. (2)): R_Y(2 pi x_k - pi) H on every site from the
+//    image's pixels, then CNOTs on the even bonds, then on the odd bonds: canonical sweep (with
+//    gates), even sweep, canonical sweep, odd sweep.  Between the two halves the even bonds are
+//    at the new dimensions and the odd ones at the old.
+enum : int { kLayerRyRzLadder = 0, kLayerHRyBrickwork = 1 };
+
 template <int S, typename T>
+__device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
+                                            int program, const double* theta, const double* phi,
+                                            const double* pix, double* trunc_err, int* status) {
+  auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
+  auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
+  SitePrefetch<S, T> pf;
+  int flags = 0;
+  if (program == kLayerHRyBrickwork) {
+    auto dmid = [&](int k) { return bond_dim(n, chi, (k & 1) ? layer : layer + 1, k); };
+    flags |= canon_sweep<S, T>(sh, st, n, dold, kGateHRy, theta, phi, pix, false, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dold, dmid, 0, trunc_err, pf);
+    flags |= canon_sweep<S, T>(sh, st, n, dmid, kGateNone, theta, phi, pix, true, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf);
+  } else {
+    flags |= canon_sweep<S, T>(sh, st, n, dold, kGateRyRz, theta, phi, pix, false, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf);
+  }
+  if (threadIdx.x == 0 && flags) status[0] |= flags;
+}
+
+// One kernel per layer program (PROG), so that each holds only its own sweeps.
+template <int S, typename T, int PROG>
 __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int chi, int layer,
                                                          const double* theta, const double* phi,
-                                                         double* trunc_err, int* status) {
+                                                         const double* pixels, double* trunc_err,
+                                                         int* status) {
   __shared__ LayerShared<S, T> sh;
   const int b = blockIdx.x;
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
-  layer_chain<S, T>(sh, st, n, chi, layer, theta, phi,
+  layer_chain<S, T>(sh, st, n, chi, layer, PROG, theta, phi,
+                    pixels ? pixels + (size_t)b * n : nullptr,
                     trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b);
 }
 
@@ -552,8 +627,8 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request
     const double* theta = uniform_ptr(r->theta) + (size_t)layer * n;
     const double* phi = uniform_ptr(r->phi) + (size_t)layer * n;
     double* te = uniform_ptr(r->trunc_err);
-    layer_chain<S, T>(sh, uniform_ptr((T*)r->state), n, chi, layer, theta, phi,
-                      te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1);
+    layer_chain<S, T>(sh, uniform_ptr((T*)r->state), n, chi, layer, kLayerRyRzLadder, theta, phi,
+                      nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1);
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = layer + 1;
   }
@@ -637,15 +712,22 @@ hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch
 }
 
 template <typename T>
-hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch,
-                        const double* theta, const double* phi, double* trunc_err, int* status,
-                        hipStream_t stream) {
+hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, int program,
+                        const double* theta, const double* phi, const double* pixels,
+                        double* trunc_err, int* status, hipStream_t stream) {
   const dim3 grid(batch), block(kLayerThreads);
   switch (S) {
-    case 2: hipLaunchKernelGGL((k_layer<2, T>), grid, block, 0, stream, state, n, chi, layer, theta, phi, trunc_err, status); break;
-    case 4: hipLaunchKernelGGL((k_layer<4, T>), grid, block, 0, stream, state, n, chi, layer, theta, phi, trunc_err, status); break;
-    case 8: hipLaunchKernelGGL((k_layer<8, T>), grid, block, 0, stream, state, n, chi, layer, theta, phi, trunc_err, status); break;
-    case 16: hipLaunchKernelGGL((k_layer<16, T>), grid, block, 0, stream, state, n, chi, layer, theta, phi, trunc_err, status); break;
+#define ANOMPS_KL(SV)                                                                              \
+  case SV:                                                                                         \
+    if (program == kLayerHRyBrickwork)                                                             \
+      hipLaunchKernelGGL((k_layer<SV, T, kLayerHRyBrickwork>), grid, block, 0, stream, state, n,   \
+                         chi, layer, theta, phi, pixels, trunc_err, status);                       \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_layer<SV, T, kLayerRyRzLadder>), grid, block, 0, stream, state, n,     \
+                         chi, layer, theta, phi, pixels, trunc_err, status);                       \
+    break;
+    ANOMPS_KL(2) ANOMPS_KL(4) ANOMPS_KL(8) ANOMPS_KL(16)
+#undef ANOMPS_KL
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -653,10 +735,10 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch,
 
 template hipError_t launch_encode<double>(double*, const double*, int, int, int, int*, hipStream_t);
 template hipError_t launch_encode<float>(float*, const double*, int, int, int, int*, hipStream_t);
-template hipError_t launch_layer<double>(double*, int, int, int, int, int, const double*,
-                                         const double*, double*, int*, hipStream_t);
-template hipError_t launch_layer<float>(float*, int, int, int, int, int, const double*,
-                                        const double*, double*, int*, hipStream_t);
+template hipError_t launch_layer<double>(double*, int, int, int, int, int, int, const double*,
+                                         const double*, const double*, double*, int*, hipStream_t);
+template hipError_t launch_layer<float>(float*, int, int, int, int, int, int, const double*,
+                                        const double*, const double*, double*, int*, hipStream_t);
 template hipError_t launch_encode_mixed<double>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_encode_mixed<float>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_layer_mixed<double>(const mps_request*, int, int, int, int*, int, hipStream_t);

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import closed_form, features as ofeat, readout as oread, mps as omps
+from oracle import paper_ansatz as opa
 from paper_2607_10280_amd import inputs
 from tests.golden_cases import hand_derived_cases
 
@@ -264,3 +265,65 @@ def test_split_bf16_contractions(A, p):
     print(f"[split-bf16] p={p} max err {err:.3e} (fp32 {err32:.3e})", flush=True)
     assert err <= SPLIT_TOL[p]
     assert err > 0  # the variant really runs (a bit-exact match would mean the FP32 path ran)
+
+
+# ------------------------------------------------------------------ the paper's own circuit
+
+
+def run_paper(A, pixels, L, pairs, chi, prec, trunc=False):
+    import torch
+    print(f"[case] paper circuit B={np.shape(pixels)[0]} n={np.shape(pixels)[1]} L={L} chi={chi} "
+          f"prec={prec} m={len(pairs)}", flush=True)
+    res = A.paper_features(pixels, L, pairs, chi, prec, return_trunc_err=trunc)
+    torch.cuda.synchronize()
+    return tuple(r.cpu().numpy() for r in res)
+
+
+@pytest.mark.parametrize("x0,L,n", [(0.0, 1, 4), (0.0, 1, 5), (0.0, 2, 5), (0.75, 1, 5), (0.5, 3, 6)])
+def test_paper_circuit_special_inputs(A, x0, L, n):
+    """Inputs whose results are worked out by hand in the oracle's pins."""
+    pairs = np.array([[i, j] for i in range(n) for j in range(i + 1, n)], dtype=np.int32)
+    x = np.full((1, n), x0)
+    out, st = run_paper(A, x, L, pairs, 8, A.PREC_FP64)
+    assert st[0] == 0
+    assert np.abs(out[0] - opa.sv_features(x[0], L, pairs)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4])
+def test_paper_circuit_exact_fp64(A, L):
+    p, n, B = 4, 16, 3
+    x = inputs.blob_images(B, p, 160 + L)
+    pairs = inputs.neighbour_pairs(p, diagonal=True)
+    out, st = run_paper(A, x, L, pairs, 16, A.PREC_FP64)
+    assert np.all(st == 0)
+    assert np.abs(out - opa.features(x, L, pairs)).max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("L,chi", [(2, 2), (3, 2), (3, 3), (4, 4), (4, 6)])
+def test_paper_circuit_truncated_fp64(A, L, chi):
+    p, n, B = 4, 16, 3
+    x = inputs.uniform_pixels(B, n, 170 + 10 * L + chi)
+    pairs = inputs.neighbour_pairs(p, diagonal=True)
+    out, st, te = run_paper(A, x, L, pairs, chi, A.PREC_FP64, trunc=True)
+    assert np.all(st == 0)
+    exact = opa.features(x, L, pairs)
+    for b in range(B):
+        m = opa.mps_simulate(x[b], L, chi)
+        ref = omps.pauli_pair_features(m, pairs)
+        errs = np.stack(m.trunc_err)
+        bound = 2.0 * np.sum(np.sqrt(2.0 * errs))
+        assert np.abs(out[b] - exact[b]).max() <= bound + 1e-9
+        if np.min(np.stack(m.gaps)) > 1e-6:
+            assert np.abs(out[b] - ref).max() <= FP64_TOL
+            assert np.abs(te[b] - errs).max() <= 1e-10
+
+
+def test_paper_circuit_49q_fp32(A):
+    """7x7 with the paper's 156 neighbour pairs, L = 4, chi = 16, complex64 + FP64 SVD."""
+    p, n, B, L = 7, 49, 2, 4
+    x = inputs.blob_images(B, p, 180)
+    pairs = inputs.neighbour_pairs(p, diagonal=True)
+    assert len(pairs) == 156
+    out, st = run_paper(A, x, L, pairs, 16, A.PREC_FP32)
+    assert np.all(st == 0)
+    assert np.abs(out - opa.features(x, L, pairs)).max() <= FP32_TOL
