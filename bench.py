@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "mixed", "serve", "grid"],
+                    choices=["headline", "mixed", "serve", "grid", "paper"],
                     help="headline: the 7x7 L=4 chi=16 batch; mixed: 4096 requests of mixed size "
                          "and depth through the persistent mixed-table launches; serve: Poisson "
                          "arrivals through the continuous-batching loop")
@@ -337,6 +337,52 @@ def run_grid(args):
                    "global_batch": B}, "cells": cells}))
 
 
+def run_paper(args):
+    """The paper's own encoding circuit (H, R_Y(2 pi x - pi), brickwork CNOTs, repeated L times)
+    on 7x7 images with its 156 neighbour pairs (horizontal, vertical, diagonal), batch 1024."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs
+    from oracle import paper_ansatz as opa
+    prec = anomps.PRECISIONS[args.precision]
+    p, B, L, chi = args.p, args.batch, args.layers, args.chi
+    n = p * p
+    x = inputs.blob_images(B, p, 2)
+    pairs = inputs.neighbour_pairs(p, diagonal=True)
+    pix = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    pd = torch.as_tensor(pairs, device="cuda")
+    real = torch.float64 if prec == anomps.PREC_FP64 else torch.float32
+    b = anomps.new_batch(n, chi, L, B, prec)
+    out = torch.empty((B, len(pairs), 15), dtype=real, device="cuda")
+
+    def step():
+        anomps.init_zero(b)
+        for _ in range(L):
+            anomps.apply_layer_program(b, anomps.LAYER_H_RY_BRICKWORK, pixels=pix)
+        anomps.pauli_pair_expect(b, pd, out)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    o = out.cpu().numpy()
+    sample = [0, B // 2, B - 1]
+    ref = opa.features(x[sample], L, pairs) if chi >= 2 ** L else opa.features(x[sample], L, pairs, chi)
+    print(json.dumps({
+        "metric": "Pauli-feature images/sec, the paper's encoding circuit, 7x7, 156 pairs",
+        "value": round(B / (ms * 1e-3), 1), "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision, "data": "synthetic",
+        "config": {"workload": f"{p}x{p} Gaussian blobs, H + R_Y(2 pi x - pi) + brickwork CNOTs, "
+                               f"L={L}, chi={chi}, {len(pairs)} pairs", "global_batch": B},
+        "max_abs_err": float(np.abs(o[sample] - ref).max()),
+        "status_nonzero": int(np.count_nonzero(b.status.cpu()))}))
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     args = parse()
@@ -349,6 +395,8 @@ def main():
         return run_serve(args)
     if args.workload == "grid":
         return run_grid(args)
+    if args.workload == "paper":
+        return run_paper(args)
     import torch
     from paper_2607_10280_amd import anomps, inputs, workload
 
