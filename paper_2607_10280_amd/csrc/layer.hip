@@ -57,9 +57,6 @@ struct LayerShared {
   cx<T> tb[2 * S * SP];       // neighbour tensor [c][t][b] at (c*2+t)*SP + b
   cd uq[2 * S * SP];          // U [r][j] at r*SP + j (ladder) or V*Sigma [j][a] at j*SP + a (sweep)
   double sig2[2 * S];
-  cd hv0[2 * S];              // leading entry of each Householder vector (QR path)
-  double htau[2 * S];         // Householder scalings tau_j (QR path)
-  cd rdiag[2 * S];            // diagonal of R (QR path)
   int rank[2 * S];            // columns in descending singular-value order
   double red[kLayerThreads / 64];
   double tiny2;               // negligible-column threshold of the last decomposition
@@ -143,8 +140,6 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
 }
 
 // One-sided (Hestenes) Jacobi on the N columns of `mat` (rows [M, MP) must be zero) in FP64.
-// Rows [ndot, M) are rotated with their columns but left out of every inner product, norm and
-// threshold (they carry the accumulated right rotations V when the matrix is [R^H; I]).
 // Column pairs follow the round-robin tournament: NP-1 rounds of NP/2 disjoint pairs per
 // sweep.  A team of T lanes owns a pair; each lane holds R rows of both columns in registers,
 // the team reduces |x|^2, |y|^2 and x^H y with DPP row moves, and every lane of the team
@@ -152,7 +147,7 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
 // tol = M eps; columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2 count as numerically zero.
 // On return sig2[c] = |w_c|^2 for c < N.  Returns kImgNoConvergence if the sweep limit hit.
 template <int S, typename T, int NP, int R>
-__device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndot) {
+__device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int P = NP / 2;
   constexpr int TM = (kLayerThreads / P) < 16 ? kLayerThreads / P : 16;
@@ -163,14 +158,13 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndo
   const bool active = q < P;
   double f = 0.0;
   for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-    const int rr = idx % MP;
-    const cd v = mat[(idx / MP) * LD + rr];
-    if (rr < ndot) f = fma(v.re, v.re, fma(v.im, v.im, f));
+    const cd v = sh.mat[(idx / MP) * LD + (idx % MP)];
+    f = fma(v.re, v.re, fma(v.im, v.im, f));
   }
   f = block_sum(f, sh.red);
   const double tiny2 = 1e-30 * f;
   if (tid == 0) sh.tiny2 = tiny2;
-  const double tol = (double)ndot * 2.220446049250313e-16;
+  const double tol = (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   bool converged = (N < 2);
   int sweep = 0;
@@ -188,14 +182,12 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndo
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         const int rr = lt + t * TM;
-        x[t] = mat[ci_ * LD + rr];
-        y[t] = mat[cj_ * LD + rr];
-        // rows at or past ndot (the accumulated V of the QR path) are rotated, not summed
-        const cd xd = rr < ndot ? x[t] : cd{0.0, 0.0};
-        gr = fma(xd.re, y[t].re, fma(xd.im, y[t].im, gr));
-        gi = fma(xd.re, y[t].im, fma(-xd.im, y[t].re, gi));
-        a = fma(xd.re, xd.re, fma(xd.im, xd.im, a));
-        if (rr < ndot) bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
+        x[t] = sh.mat[ci_ * LD + rr];
+        y[t] = sh.mat[cj_ * LD + rr];
+        gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
+        gi = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, gi));
+        a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
+        bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
       }
       a = team_sum<TM>(a);
       bb = team_sum<TM>(bb);
@@ -219,8 +211,8 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndo
         for (int tt = 0; tt < R; ++tt) {
           const int rr = lt + tt * TM;
           const cd ye = cmul(e, y[tt]);
-          mat[ci * LD + rr] = cd{fma(c, x[tt].re, -s * ye.re), fma(c, x[tt].im, -s * ye.im)};
-          mat[cj * LD + rr] = cd{fma(s, x[tt].re, c * ye.re), fma(s, x[tt].im, c * ye.im)};
+          sh.mat[ci * LD + rr] = cd{fma(c, x[tt].re, -s * ye.re), fma(c, x[tt].im, -s * ye.im)};
+          sh.mat[cj * LD + rr] = cd{fma(s, x[tt].re, c * ye.re), fma(s, x[tt].im, c * ye.im)};
         }
       }
       __syncthreads();
@@ -234,8 +226,8 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndo
   }
   for (int col = tid; col < N; col += kLayerThreads) {
     double s2 = 0.0;
-    for (int rr = 0; rr < ndot; ++rr) {
-      const cd v = mat[col * LD + rr];
+    for (int rr = 0; rr < MP; ++rr) {
+      const cd v = sh.mat[col * LD + rr];
       s2 = fma(v.re, v.re, fma(v.im, v.im, s2));
     }
     sh.sig2[col] = s2;
@@ -245,13 +237,13 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndo
 }
 
 template <int S, typename T>
-__device__ int jacobi_columns(LayerShared<S, T>& sh, cd* mat, int M, int N, int ndot) {
+__device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   const JShape js = jacobi_shape(M, N);
 #define ANOMPS_JT(NPV, RV)                                                           \
   if (js.NP == NPV && js.R == RV) {                                                  \
     if constexpr (NPV <= 2 * S && RV * ((kLayerThreads / (NPV / 2)) < 16 ? kLayerThreads / (NPV / 2) : 16) <= \
                                        LayerShared<S, T>::LD)                        \
-      return jacobi_tile<S, T, NPV, RV>(sh, mat, M, N, ndot);                                \
+      return jacobi_tile<S, T, NPV, RV>(sh, M, N);                                  \
   }
 #define ANOMPS_JN(NPV) ANOMPS_JT(NPV, 1) ANOMPS_JT(NPV, 2) ANOMPS_JT(NPV, 4) ANOMPS_JT(NPV, 8)
   ANOMPS_JN(2) ANOMPS_JN(4) ANOMPS_JN(8) ANOMPS_JN(16) ANOMPS_JN(32)
@@ -290,157 +282,6 @@ __device__ __forceinline__ Gate2 site_gate(int mode, int k, const double* theta,
     g.u11 = cscale(ep, ct);
   }
   return g;
-}
-
-// ---- QR-preconditioned SVD of a CNOT bond (N <= S columns, N <= M <= 32 rows).
-// Column-pivoted Householder QR  Theta' P = Q R, then one-sided Jacobi on Y = [R^H; I]:
-// R^H V = W with orthogonal columns w_c, so Theta' P = (Q V) W^H and the left singular vectors
-// are Q V (orthonormal by construction), the singular values |w_c|.  Jacobi on R^H after a
-// pivoted QR needs markedly fewer sweeps than on Theta' itself (Drmac and Veselic's
-// preconditioning), and its inner products run over N rows instead of M.
-// Lanes: group g = tid/4 owns one column, lane q = tid%4 of the group owns rows 8q..8q+7.
-constexpr int kQrRows = 8;
-
-template <int S, typename T>
-__device__ __forceinline__ int qr_jacobi(LayerShared<S, T>& sh, int M, int N) {
-  constexpr int LD = LayerShared<S, T>::LD;
-  const int tid = threadIdx.x, g = tid >> 2, q = tid & 3;
-  const bool mine = g < N;
-  cd x[kQrRows];
-#pragma unroll
-  for (int i = 0; i < kQrRows; ++i) {
-    const int r = q * kQrRows + i;
-    x[i] = (mine && r < M) ? sh.mat[g * LD + r] : cd{0.0, 0.0};
-  }
-  __syncthreads();  // every column is in registers before mat columns are reused
-  bool chosen = false;
-  int slot = -1;
-  for (int j = 0; j < N; ++j) {
-    // squared norms of the remaining columns over rows j..M-1; pivot = the largest
-    double nr = 0.0;
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i)
-      if (q * kQrRows + i >= j) nr = fma(x[i].re, x[i].re, fma(x[i].im, x[i].im, nr));
-    nr = team_sum<4>(nr);
-    if (q == 0 && mine) sh.sig2[g] = chosen ? -1.0 : nr;
-    __syncthreads();
-    int p = 0;
-    double best = -2.0;
-    for (int c = 0; c < N; ++c) {
-      const double v = sh.sig2[c];
-      if (v > best) {
-        best = v;
-        p = c;
-      }
-    }
-    if (g == p) {  // the pivot column becomes Householder vector j (rows j..M-1 of mat column j)
-#pragma unroll
-      for (int i = 0; i < kQrRows; ++i) {
-        const int r = q * kQrRows + i;
-        if (r >= j && r < M) sh.mat[j * LD + r] = x[i];
-      }
-      chosen = true;
-      slot = j;
-    }
-    __syncthreads();
-    const double alpha = sqrt(best > 0.0 ? best : 0.0);
-    const cd x0 = sh.mat[j * LD + j];
-    const double ax0 = sqrt(fma(x0.re, x0.re, x0.im * x0.im));
-    const cd beta = ax0 > 0.0 ? cd{-alpha * x0.re / ax0, -alpha * x0.im / ax0} : cd{-alpha, 0.0};
-    const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax0)) : 0.0;
-    const cd v0{x0.re - beta.re, x0.im - beta.im};
-    if (tid == 0) {
-      sh.rdiag[j] = beta;
-      sh.hv0[j] = v0;
-      sh.htau[j] = tau;
-    }
-    // reflect the remaining columns: x -= tau v (v^H x) over rows j..M-1
-    cd vr[kQrRows];
-    cd w{0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i) {
-      const int r = q * kQrRows + i;
-      vr[i] = (r < j || r >= M) ? cd{0.0, 0.0} : (r == j ? v0 : sh.mat[j * LD + r]);
-      cfmac(w, vr[i], x[i]);
-    }
-    w.re = team_sum<4>(w.re);
-    w.im = team_sum<4>(w.im);
-    if (mine && !chosen) {
-      const cd tw{tau * w.re, tau * w.im};
-#pragma unroll
-      for (int i = 0; i < kQrRows; ++i) {
-        const cd d = cmul(vr[i], tw);
-        x[i] = cd{x[i].re - d.re, x[i].im - d.im};
-      }
-    }
-    __syncthreads();
-  }
-  // Y = [R^H; I] in mat columns S..S+N-1: Y[r][i] = conj(R[i][r]); column `slot` of R holds
-  // R[i][slot] (i < slot) in its rows i, final since step i; the diagonal is beta_i.
-  cd* Y = sh.mat + S * LD;
-  const int MPy = jacobi_shape(2 * N, N).MP;
-  for (int idx = tid; idx < N * MPy; idx += kLayerThreads) {
-    const int i = idx / MPy, r = idx % MPy;
-    cd v{0.0, 0.0};
-    if (r == i) v = cconj(sh.rdiag[i]);
-    else if (r == N + i) v = cd{1.0, 0.0};
-    Y[i * LD + r] = v;
-  }
-  __syncthreads();
-  if (slot >= 0) {
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i) {
-      const int r = q * kQrRows + i;  // row r of this column = R[r][slot]
-      if (r < slot) Y[r * LD + slot] = cconj(x[i]);
-    }
-  }
-  __syncthreads();
-  return jacobi_columns<S, T>(sh, Y, 2 * N, N, N);
-}
-
-// U = Q V for the D kept columns (rank order), written to uq[r*SP + j].
-template <int S, typename T>
-__device__ __forceinline__ void qr_apply_u(LayerShared<S, T>& sh, int M, int N, int D) {
-  constexpr int LD = LayerShared<S, T>::LD;
-  constexpr int SP = LayerShared<S, T>::SP;
-  const int tid = threadIdx.x, g = tid >> 2, q = tid & 3;
-  const bool mine = g < D;
-  const int c = mine ? sh.rank[g] : 0;
-  const cd* Y = sh.mat + S * LD;
-  cd u[kQrRows];
-#pragma unroll
-  for (int i = 0; i < kQrRows; ++i) {
-    const int r = q * kQrRows + i;
-    u[i] = (mine && r < N) ? Y[c * LD + N + r] : cd{0.0, 0.0};
-  }
-  for (int j = N - 1; j >= 0; --j) {  // Q = H_0 H_1 ... H_{N-1}
-    const double tau = sh.htau[j];
-    if (tau == 0.0) continue;
-    const cd v0 = sh.hv0[j];
-    cd vr[kQrRows];
-    cd w{0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i) {
-      const int r = q * kQrRows + i;
-      vr[i] = (r < j || r >= M) ? cd{0.0, 0.0} : (r == j ? v0 : sh.mat[j * LD + r]);
-      cfmac(w, vr[i], u[i]);
-    }
-    w.re = team_sum<4>(w.re);
-    w.im = team_sum<4>(w.im);
-    const cd tw{tau * w.re, tau * w.im};
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i) {
-      const cd d = cmul(vr[i], tw);
-      u[i] = cd{u[i].re - d.re, u[i].im - d.im};
-    }
-  }
-  if (mine) {
-#pragma unroll
-    for (int i = 0; i < kQrRows; ++i) {
-      const int r = q * kQrRows + i;
-      if (r < M) sh.uq[r * SP + g] = u[i];
-    }
-  }
 }
 
 // Apply a one-qubit gate to the physical index of the (Dl x 2 x Dr) tensor in ta.
@@ -545,7 +386,7 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
       sh.mat[a * LD + rr] = v;
     }
     __syncthreads();
-    flags |= jacobi_columns<S, T>(sh, sh.mat, M, N, M);
+    flags |= jacobi_columns<S, T>(sh, M, N);
     const double tiny2 = sh.tiny2;
     // Right-canonical rows q_a^H and V*Sigma = t Q.
     T* slot = st + (size_t)k * SLOT;
@@ -620,11 +461,7 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
       }
     }
     __syncthreads();
-    const bool qr = N >= 8 && N <= S && M >= N;
-    if (qr)
-      flags |= qr_jacobi<S, T>(sh, M, N);
-    else
-      flags |= jacobi_columns<S, T>(sh, sh.mat, M, N, M);
+    flags |= jacobi_columns<S, T>(sh, M, N);
     const double tiny2 = sh.tiny2;
     // Rank columns by singular value (descending, ties by index; NaN counts as zero); thread c
     // owns column c (N <= 2S <= 64).
@@ -649,11 +486,8 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
     if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
     const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
     if (cx && tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
-    // U columns = normalised kept columns of W (numerically zero columns become zero), or
-    // Q V on the QR path.
-    if (qr) {
-      qr_apply_u<S, T>(sh, M, N, D);
-    } else {
+    // U columns = normalised kept columns of W (numerically zero columns become zero).
+    {
       const FastDiv fd(D);
       for (int idx = tid; idx < M * D; idx += kLayerThreads) {
         const int r = fd.q(idx), j = fd.r(idx);
