@@ -205,6 +205,31 @@ int mps_ano_readout(const void* pauli, const void* coeff, const void* W, const v
                     int32_t batch, int32_t m, int32_t out_dim, void* y, int32_t is_f64,
                     hipStream_t stream);
 
+/*
+ * One training step of the observables and the linear layer on cached features (§II-C: the
+ * expectations are computed once and cached; §II-D: separate Adam optimizers for (A, B, D) and
+ * (W, b)).  Loss: the MSE term of Eq. (7) only (the LPIPS term needs a trained network),
+ *   L = mean_{b,o} (y_hat[b][o] - target[b][o])^2,  y_hat from (A, B, D, W, bias) as in
+ *   mps_ano_coeffs / mps_ano_readout.
+ * Gradients by the chain rule through Eq. (6), (5), (4); then Adam with bias correction
+ * (Kingma & Ba): m = beta1 m + (1-beta1) g, v = beta2 v + (1-beta2) g^2,
+ * p -= lr m/(1-beta1^step) / (sqrt(v/(1-beta2^step)) + eps), lr = lr_obs for A, B, D and lr_lin
+ * for W, bias.
+ *  pauli [batch][m][15], target [batch][out_dim]: device, read only.
+ *  A [m][6], B [m][6], D [m][4], W [out_dim][m], bias [out_dim]: device, updated in place.
+ *  adam_m, adam_v: device [16 m + out_dim m + out_dim], the moments of A, B, D, W, bias packed in
+ *    that order; zero before step 1, caller-owned between steps.
+ *  loss: device [1], receives L before the update.  workspace: device, >=
+ *    mps_ano_train_workspace_bytes(batch, m, out_dim, is_f64).  Real type float64 if is_f64.
+ * Errors: MPS_ERR_INVALID_ARG (sizes, step < 1, Adam constants, NULL), MPS_ERR_CAPACITY (m > 4096).
+ */
+size_t mps_ano_train_workspace_bytes(int32_t batch, int32_t m, int32_t out_dim, int32_t is_f64);
+int mps_ano_train_step(const void* pauli, const void* target, void* A, void* B, void* D, void* W,
+                       void* bias, void* adam_m, void* adam_v, int32_t batch, int32_t m,
+                       int32_t out_dim, int32_t step, double lr_obs, double lr_lin, double beta1,
+                       double beta2, double eps, void* loss, void* workspace, int32_t is_f64,
+                       hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------
  * Mixed requests (continuous batching).  A request is one image with its own n_sites, chi,
  * layer count, precision, angles, pair list and buffers; a table of requests runs through one

@@ -105,6 +105,10 @@ EXPORTS = {
     "mps_pauli_pair_expect_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan),
                                                    ctypes.c_void_p]),
     "mps_set_mixed_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "mps_ano_train_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 4),
+    "mps_ano_train_step": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_int32] * 4 +
+                           [ctypes.c_double] * 5 + [ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_int32, ctypes.c_void_p]),
     "mps_last_error": (ctypes.c_char_p, []),
 }
 
@@ -238,6 +242,38 @@ def ano_readout(pauli, coeff, W, bias, y, stream=None) -> None:
     is_f64 = int(y.dtype.itemsize == 8)
     _check(lib().mps_ano_readout(_ptr(pauli), _ptr(coeff), _ptr(W), _ptr(bias), batch, m,
                                  out_dim, _ptr(y), is_f64, _stream(stream)))
+
+
+class AnoTrainer:
+    """Device state of the observable/readout training on cached features: parameters, Adam
+    moments and workspace (all torch tensors); `step` calls mps_ano_train_step."""
+
+    def __init__(self, A, B, D, W, bias, batch: int, lr_obs=1e-2, lr_lin=1e-2, beta1=0.9,
+                 beta2=0.999, eps=1e-8):
+        import torch
+        self.params = [A, B, D, W, bias]
+        dt, dev = W.dtype, W.device
+        m, out_dim = A.shape[0], W.shape[0]
+        n = 16 * m + out_dim * m + out_dim
+        self.mom = torch.zeros(n, dtype=dt, device=dev)
+        self.vel = torch.zeros(n, dtype=dt, device=dev)
+        self.loss = torch.zeros(1, dtype=dt, device=dev)
+        self.is_f64 = int(dt == torch.float64)
+        nb = int(lib().mps_ano_train_workspace_bytes(batch, m, out_dim, self.is_f64))
+        if nb == 0:
+            raise MpsError(-1, "invalid training sizes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.batch, self.m, self.out_dim = batch, m, out_dim
+        self.hyper = (lr_obs, lr_lin, beta1, beta2, eps)
+        self.t = 0
+
+    def step(self, pauli, target, stream=None):
+        self.t += 1
+        _check(lib().mps_ano_train_step(_ptr(pauli), _ptr(target), *[_ptr(p) for p in self.params],
+                                        _ptr(self.mom), _ptr(self.vel), self.batch, self.m,
+                                        self.out_dim, self.t, *self.hyper, _ptr(self.loss),
+                                        _ptr(self.ws), self.is_f64, _stream(stream)))
+        return self.loss
 
 
 def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_FP32,

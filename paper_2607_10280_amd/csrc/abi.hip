@@ -361,6 +361,36 @@ int mps_set_mixed_tuning(int32_t bucket, int32_t blocks_per_cu) {
   return ok();
 }
 
+size_t mps_ano_train_workspace_bytes(int32_t batch, int32_t m, int32_t out_dim, int32_t is_f64) {
+  if (batch < 1 || m < 1 || m > 4096 || out_dim < 1) return 0;
+  return train_workspace_elems(batch, m, out_dim) * (is_f64 ? sizeof(double) : sizeof(float));
+}
+
+int mps_ano_train_step(const void* pauli, const void* target, void* A, void* B, void* D, void* W,
+                       void* bias, void* adam_m, void* adam_v, int32_t batch, int32_t m,
+                       int32_t out_dim, int32_t step, double lr_obs, double lr_lin, double beta1,
+                       double beta2, double eps, void* loss, void* workspace, int32_t is_f64,
+                       hipStream_t stream) {
+  if (batch < 1 || m < 1 || out_dim < 1) return fail(MPS_ERR_INVALID_ARG, "batch, m and out_dim must be >= 1");
+  if (m > 4096) return fail(MPS_ERR_CAPACITY, "m=%d exceeds 4096", m);
+  if (step < 1) return fail(MPS_ERR_INVALID_ARG, "step=%d: Adam steps count from 1", step);
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0))
+    return fail(MPS_ERR_INVALID_ARG, "Adam needs 0 <= beta1, beta2 < 1 and eps > 0");
+  if (!pauli || !target || !A || !B || !D || !W || !bias || !adam_m || !adam_v || !loss || !workspace)
+    return fail(MPS_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = is_f64
+      ? launch_train_step<double>((const double*)pauli, (const double*)target, (double*)A, (double*)B,
+                                  (double*)D, (double*)W, (double*)bias, (double*)adam_m,
+                                  (double*)adam_v, batch, m, out_dim, step, lr_obs, lr_lin, beta1,
+                                  beta2, eps, (double*)loss, (double*)workspace, stream)
+      : launch_train_step<float>((const float*)pauli, (const float*)target, (float*)A, (float*)B,
+                                 (float*)D, (float*)W, (float*)bias, (float*)adam_m, (float*)adam_v,
+                                 batch, m, out_dim, step, lr_obs, lr_lin, beta1, beta2, eps,
+                                 (float*)loss, (float*)workspace, stream);
+  if (e != hipSuccess) return check_hip(e, "training step launch");
+  return ok();
+}
+
 const char* mps_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

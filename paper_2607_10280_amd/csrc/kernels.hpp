@@ -55,4 +55,12 @@ template <typename R>
 hipError_t launch_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int batch,
                           int m, int out_dim, R* y, hipStream_t stream);
 
+// One training step on cached features (train.hip); workspace in elements of the real type.
+size_t train_workspace_elems(int batch, int m, int out_dim);
+template <typename R>
+hipError_t launch_train_step(const R* pauli, const R* target, R* A, R* B, R* D, R* W, R* bias,
+                             R* mom, R* vel, int batch, int m, int out_dim, int step, double lr_obs,
+                             double lr_lin, double beta1, double beta2, double eps, R* loss,
+                             R* ws, hipStream_t stream);
+
 }  // namespace anomps
