@@ -1,0 +1,61 @@
+"""Host-side logic of the serving loop and the input generators (CPU only)."""
+import numpy as np
+import pytest
+
+from paper_2607_10280_amd import inputs
+from paper_2607_10280_amd.serving import ALIGN, ArenaAllocator
+
+
+def test_arena_first_fit_and_coalescing():
+    a = ArenaAllocator(10 * ALIGN)
+    x = a.alloc(3 * ALIGN)
+    y = a.alloc(2 * ALIGN + 1)       # rounded up to 3 blocks
+    z = a.alloc(ALIGN)
+    assert (x, y, z) == (0, 3 * ALIGN, 6 * ALIGN) and a.used == 7 * ALIGN
+    assert a.alloc(4 * ALIGN) is None  # only 3 blocks left at the end
+    a.release(y, 2 * ALIGN + 1)
+    assert a.alloc(3 * ALIGN) == 3 * ALIGN  # the freed hole is reused first
+    a.release(3 * ALIGN, 3 * ALIGN)
+    a.release(x, 3 * ALIGN)
+    a.release(z, ALIGN)
+    assert a.free == [(0, 10 * ALIGN)] and a.used == 0  # everything coalesced back
+
+
+def test_arena_random_alloc_free_never_overlaps():
+    rng = np.random.Generator(np.random.PCG64(5))
+    a = ArenaAllocator(200 * ALIGN)
+    live = {}
+    for _ in range(2000):
+        if live and rng.random() < 0.45:
+            off = list(live)[rng.integers(len(live))]
+            a.release(off, live.pop(off))
+        else:
+            n = int(rng.integers(1, 20 * ALIGN))
+            off = a.alloc(n)
+            if off is not None:
+                live[off] = n
+        spans = sorted((o, o + -(-n // ALIGN) * ALIGN) for o, n in live.items())
+        assert all(s1[1] <= s2[0] for s1, s2 in zip(spans, spans[1:]))
+        assert a.used == sum(e - s for s, e in spans)
+        free = sum(ln for _, ln in a.free)
+        assert free + a.used == a.size
+
+
+def test_request_mix_and_arrivals_are_seeded():
+    m1 = inputs.request_mix(50, [7, 8], [1, 2, 3], [2, 16], 9)
+    m2 = inputs.request_mix(50, [7, 8], [1, 2, 3], [2, 16], 9)
+    assert m1 == m2
+    assert {q["p"] for q in m1} <= {7, 8} and {q["chi"] for q in m1} <= {2, 16}
+    t = inputs.poisson_arrivals(20000, 500.0, 3)
+    assert np.all(np.diff(t) > 0)
+    assert abs(len(t) / t[-1] - 500.0) < 15.0  # rate within ~3 sigma
+
+
+@pytest.mark.parametrize("p", [2, 3, 7])
+def test_diagonal_pairs(p):
+    pr = inputs.neighbour_pairs(p, diagonal=True)
+    assert len(pr) == 2 * p * (p - 1) + 2 * (p - 1) ** 2
+    assert len({tuple(x) for x in pr}) == len(pr) and np.all(pr[:, 0] < pr[:, 1])
+    for i, j in pr:  # grid neighbours (8-neighbourhood)
+        ri, ci, rj, cj = i // p, i % p, j // p, j % p
+        assert max(abs(ri - rj), abs(ci - cj)) == 1
