@@ -252,6 +252,151 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   return kImgNoConvergence;  // unreachable for shapes within the slot
 }
 
+// Householder QR of A = t^H (M rows, N <= M columns, column-major in `mat`, rows [0, M) read)
+// in FP64, used by the canonical sweep: t = L Q with L = R^H lower-triangular (N x N) and
+// Q = (first N columns of H_0 ... H_{N-1})^H with orthonormal rows.  A team of TM lanes owns
+// column c; lane lt holds rows lt + t*TM (R per lane) in registers.  Step j reflects rows [j, M)
+// of column j onto beta_j e_j with H_j = I - coef_j v_j v_j^H (beta_j = -e^{i arg a_jj} |a_j|,
+// the sign that avoids cancellation), publishes v_j in mat column j and coef_j in sig2[j], and
+// every later column takes the reflection.  A column whose remaining part has |.|^2 <= 1e-30
+// |A|_F^2 is left as it is (H_j = I).  Q is then formed by applying H_{N-1}, ..., H_0 to the
+// first N unit vectors.
+// Out: uq[j*SP + a] = L[j][a]; rows of Q conjugated into the site slot as [a][s][b] (row index
+// r = s*Dr + b).
+template <int S, typename T, int NC, int R>
+__device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  constexpr int TM = (kLayerThreads / NC) < 16 ? kLayerThreads / NC : 16;
+  static_assert(R * TM <= LD, "tile rows exceed the LDS column");
+  const int tid = threadIdx.x;
+  const int c = tid / TM, lt = tid % TM;
+  const bool own = c < N;
+  cd x[R];
+  double f = 0.0;
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int rr = lt + t * TM;
+    x[t] = (own && rr < M) ? sh.mat[c * LD + rr] : cd{0.0, 0.0};
+    f = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, f));
+  }
+  const double tiny2 = 1e-30 * block_sum(f, sh.red);
+  for (int j = 0; j < N; ++j) {
+    // |rows >= j|^2 and the diagonal entry of this team's column (used by team j only).
+    double a2 = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int rr = lt + t * TM;
+      if (rr >= j) a2 = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a2));
+      if (rr == j) { dr = x[t].re; di = x[t].im; }
+    }
+    a2 = team_sum<TM>(a2);
+    dr = team_sum<TM>(dr);
+    di = team_sum<TM>(di);
+    if (c == j) {
+      cd beta{dr, di}, v0{dr, di};
+      double coef = 0.0;
+      if (a2 > tiny2) {
+        const double alpha = a2 * rsqrt_full(a2);
+        const double d2 = fma(dr, dr, di * di);
+        const double rd = d2 > 0.0 ? rsqrt_full(d2) : 0.0;
+        const double ad = d2 * rd;                          // |a_jj|
+        const cd u = d2 > 0.0 ? cd{dr * rd, di * rd} : cd{1.0, 0.0};
+        beta = cd{-u.re * alpha, -u.im * alpha};
+        v0 = cd{u.re * (ad + alpha), u.im * (ad + alpha)};
+        coef = 1.0 / (alpha * (alpha + ad));                // 2 / |v|^2
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int rr = lt + t * TM;
+        cd v = x[t];
+        if (rr < j) v = cd{0.0, 0.0};
+        if (rr == j) v = v0;
+        if (rr < LD) sh.mat[j * LD + rr] = v;
+        // Column j of R: entries above the diagonal, beta on it; L = R^H.
+        if (rr < N) sh.uq[j * SP + rr] = rr < j ? cconj(x[t]) : (rr == j ? cconj(beta) : cd{0.0, 0.0});
+      }
+      if (lt == 0) sh.sig2[j] = coef;
+    }
+    __syncthreads();
+    if (c > j && own) {
+      const double coef = sh.sig2[j];
+      cd v[R];
+      double gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        v[t] = sh.mat[j * LD + lt + t * TM];
+        gr = fma(v[t].re, x[t].re, fma(v[t].im, x[t].im, gr));     // v^H x
+        gi = fma(v[t].re, x[t].im, fma(-v[t].im, x[t].re, gi));
+      }
+      gr = team_sum<TM>(gr) * coef;
+      gi = team_sum<TM>(gi) * coef;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        x[t].re -= gr * v[t].re - gi * v[t].im;
+        x[t].im -= gr * v[t].im + gi * v[t].re;
+      }
+    }
+  }
+  // Q columns: e_c through H_{N-1}, ..., H_0 (column c only meets H_j for j <= c).
+#pragma unroll
+  for (int t = 0; t < R; ++t) x[t] = cd{(lt + t * TM == c) ? 1.0 : 0.0, 0.0};
+  for (int j = N - 1; j >= 0; --j) {
+    const double coef = sh.sig2[j];
+    cd v[R];
+    double gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      v[t] = sh.mat[j * LD + lt + t * TM];
+      gr = fma(v[t].re, x[t].re, fma(v[t].im, x[t].im, gr));
+      gi = fma(v[t].re, x[t].im, fma(-v[t].im, x[t].re, gi));
+    }
+    gr = team_sum<TM>(gr) * coef;
+    gi = team_sum<TM>(gi) * coef;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      x[t].re -= gr * v[t].re - gi * v[t].im;
+      x[t].im -= gr * v[t].im + gi * v[t].re;
+    }
+  }
+  // Row c of Q = conj(column c of the product).
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int rr = lt + t * TM;
+      if (rr < M) {
+        const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
+        store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(x[t]));
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__host__ __device__ inline int lq_rows_per_lane(int M, int N) {
+  const int nc = pow2ceil(N < 1 ? 1 : N);
+  const int tm = (kLayerThreads / nc) < 16 ? kLayerThreads / nc : 16;
+  return pow2ceil((M + tm - 1) / tm);
+}
+
+template <int S, typename T>
+__device__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
+  const int nc = pow2ceil(N < 1 ? 1 : N), r = lq_rows_per_lane(M, N);
+#define ANOMPS_LQ(NCV, RV)                                                                  \
+  if (nc == NCV && r == RV) {                                                              \
+    if constexpr (NCV <= S && RV * ((kLayerThreads / NCV) < 16 ? kLayerThreads / NCV : 16) <= \
+                                  LayerShared<S, T>::LD) {                                 \
+      householder_lq<S, T, NCV, RV>(sh, M, N, Dr, slot);                                   \
+      return 0;                                                                            \
+    }                                                                                      \
+  }
+#define ANOMPS_LQN(NCV) ANOMPS_LQ(NCV, 1) ANOMPS_LQ(NCV, 2) ANOMPS_LQ(NCV, 4) ANOMPS_LQ(NCV, 8)
+  ANOMPS_LQN(1) ANOMPS_LQN(2) ANOMPS_LQN(4) ANOMPS_LQN(8) ANOMPS_LQN(16)
+#undef ANOMPS_LQN
+#undef ANOMPS_LQ
+  return kImgNoConvergence;  // unreachable for shapes within the slot
+}
+
 // One-qubit gates of a layer program, per site k.
 enum : int { kGateNone = 0, kGateRyRz = 1, kGateHRy = 2 };
 struct Gate2 {
@@ -372,46 +517,20 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
     const int Dl = dims(k - 1), Dr = dims(k), Dll = dims(k - 2);
     pf.load(st + (size_t)(k - 1) * SLOT, Dll, Dl);
     if (mode != kGateNone) apply_gate<S, T>(sh, Dl, Dr, site_gate(mode, k, theta, phi, pix));
-    // mat = t^H: rows (s, b) -> s*Dr + b, columns a; rows [M, MP) zero.
+    // mat = t^H: rows (s, b) -> s*Dr + b, columns a.
     const int M = 2 * Dr, N = Dl;
-    const int MP = jacobi_shape(M, N).MP;
-    const FastDiv fmp(MP);
-    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-      const int a = fmp.q(idx), rr = fmp.r(idx);
-      cd v{0.0, 0.0};
-      if (rr < M) {
-        const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
-        v = cconj(sh.ta[(a * 2 + s_) * SP + b]);
-      }
-      sh.mat[a * LD + rr] = v;
-    }
-    __syncthreads();
-    flags |= jacobi_columns<S, T>(sh, M, N);
-    const double tiny2 = sh.tiny2;
-    // Right-canonical rows q_a^H and V*Sigma = t Q.
-    T* slot = st + (size_t)k * SLOT;
-    const FastDiv fm(M), fn(N), fdl(Dl);
+    const FastDiv fm(M);
     for (int idx = tid; idx < N * M; idx += kLayerThreads) {
       const int a = fm.q(idx), rr = fm.r(idx);
-      const int s = rr >= Dr, b = rr - (s ? Dr : 0);
-      const double s2 = sh.sig2[a];
-      cd v{0.0, 0.0};
-      if (s2 > tiny2) v = cscale(cconj(sh.mat[a * LD + rr]), rsqrt_full(s2));
-      store_c<T, double>(slot, (size_t)(a * 2 + s) * S + b, v);
+      const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
+      sh.mat[a * LD + rr] = cconj(sh.ta[(a * 2 + s_) * SP + b]);
     }
-    for (int idx = tid; idx < N * N; idx += kLayerThreads) {
-      const int j = fn.q(idx), a = fn.r(idx);
-      const double s2 = sh.sig2[a];
-      cd acc{0.0, 0.0};
-      if (s2 > tiny2) {
-        for (int b = 0; b < Dr; ++b) cfma(acc, sh.ta[(j * 2) * SP + b], sh.mat[a * LD + b]);
-        for (int b = 0; b < Dr; ++b) cfma(acc, sh.ta[(j * 2 + 1) * SP + b], sh.mat[a * LD + Dr + b]);
-        acc = cscale(acc, rsqrt_full(s2));
-      }
-      sh.uq[j * SP + a] = acc;
-    }
+    __syncthreads();
+    // t = L Q: Q (right-canonical rows) goes to site k, L to uq.
+    flags |= lq_columns<S, T>(sh, M, N, Dr, st + (size_t)k * SLOT);
     pf.commit(sh.tb);
     __syncthreads();
+    const FastDiv fdl(Dl);
     for (int idx = tid; idx < Dll * 2 * Dl; idx += kLayerThreads) {
       const int row = fdl.q(idx), a = fdl.r(idx);
       cd acc{0.0, 0.0};
