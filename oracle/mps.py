@@ -128,7 +128,7 @@ def left_envs(a: list) -> list:
     """L_k (ket index, bra index) = contraction of sites 0..k-1 with their conjugates."""
     envs = [np.ones((1, 1), dtype=np.complex128)]
     for t in a:
-        envs.append(np.einsum("ab,asc,bsd->cd", envs[-1], t, t.conj()))
+        envs.append(np.einsum("ab,asc,bsd->cd", envs[-1], t, t.conj(), optimize=True))
     return envs
 
 
@@ -139,17 +139,18 @@ def right_envs(a: list) -> list:
     envs[n] = np.ones((1, 1), dtype=np.complex128)
     for k in range(n - 1, -1, -1):
         t = a[k]
-        envs[k] = np.einsum("asc,cd,bsd->ab", t, envs[k + 1], t.conj())
+        envs[k] = np.einsum("asc,cd,bsd->ab", t, envs[k + 1], t.conj(), optimize=True)
     return envs
 
 
 def pair_rdm(a: list, lenv: list, renv: list, i: int, j: int) -> np.ndarray:
     """rho_ij (4x4, index s_i*2 + s_j): open with L_i and A[i], carry through the transfer
     matrices of sites i+1..j-1, close with A[j] and R_{j+1}."""
-    f = np.einsum("ab,asc,bud->sucd", lenv[i], a[i], a[i].conj())
+    f = np.einsum("ab,asc,bud->sucd", lenv[i], a[i], a[i].conj(), optimize=True)
     for k in range(i + 1, j):
-        f = np.einsum("sucd,cxe,dxf->suef", f, a[k], a[k].conj())
-    rho = np.einsum("sucd,ctb,dvf,bf->stuv", f, a[j], a[j].conj(), renv[j + 1])
+        # transfer map of site k on every (s, u) block: F <- sum_x A_x^T F conj(A_x)
+        f = sum(a[k][:, x, :].T @ f @ a[k][:, x, :].conj() for x in range(2))
+    rho = np.einsum("sucd,ctb,dvf,bf->stuv", f, a[j], a[j].conj(), renv[j + 1], optimize=True)
     return rho.reshape(4, 4)
 
 
