@@ -68,8 +68,14 @@ enum {
   MPS_IMG_NO_CONVERGENCE = 2  /* a Jacobi SVD hit its sweep limit (result still written) */
 };
 
-/* Largest bond dimension this build keeps (after the min with 2^layers and the chain ends). */
-#define MPS_MAX_BOND 16
+/* Largest bond dimension this build keeps (after the min with 2^layers and the chain ends).
+ * Slots up to 16 run one wavefront per image with the bond's matrices in LDS; slots 32, 64 and
+ * 128 run one 256-lane workgroup per image with the bond's matrices (up to 256 x 256
+ * complex128) in an FP64 workspace that the library places in the env buffer (see
+ * mps_env_bytes).  Both use the same arithmetic and truncation rule.  Mixed request tables
+ * take slots up to MPS_MIXED_MAX_SLOT. */
+#define MPS_MAX_BOND 128
+#define MPS_MIXED_MAX_SLOT 16
 /* Largest number of sites. */
 #define MPS_MAX_SITES 1024
 
@@ -93,6 +99,10 @@ int32_t mps_slot_dim(int32_t n_sites, int32_t chi, int32_t n_layers);
  *          ((a*2 + s)*S + b).  Entries outside the corner are never read.
  *  env   : [batch][2][n_sites+1][S][S] complex: left environments L_0..L_n then right
  *          environments R_0..R_n (ket index first).  Filled by mps_pauli_pair_expect.
+ *          For S > 16 the buffer continues (at the next 256-byte boundary) with an FP64
+ *          workspace of 48 S^2 complex128 elements (rounded up to 64) per image, which
+ *          mps_apply_layer and mps_pauli_pair_expect overwrite; env is then also required by
+ *          the layer calls.
  */
 size_t mps_state_bytes(int32_t n_sites, int32_t chi, int32_t n_layers, int32_t batch, int32_t precision);
 size_t mps_env_bytes(int32_t n_sites, int32_t chi, int32_t n_layers, int32_t batch, int32_t precision);
@@ -131,7 +141,8 @@ int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream);
  *  theta, phi : device [n_sites] float64, this layer's angles (shared by the batch).
  *  trunc_err  : device [batch][n_sites-1] float64 or NULL; receives the discarded weight
  *               sum_discarded sigma^2 / sum sigma^2 of every bond of this layer.
- * Errors: MPS_ERR_INVALID_ARG if layers_done == n_layers or the batch was not initialised.
+ * Errors: MPS_ERR_INVALID_ARG if layers_done == n_layers, the batch was not initialised, or
+ *   env is NULL for a slot wider than 16.
  */
 int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
                     hipStream_t stream);
@@ -255,7 +266,8 @@ typedef struct {
   int32_t* ctrl;          /* device [2]: ctrl[0] = layers applied so far, ctrl[1] = MPS_IMG_* flags */
 } mps_request;
 
-/* Requests are grouped by bucket = 4*(precision == FP32) + log2(S) - 1, S = mps_slot_dim(...). */
+/* Requests are grouped by bucket = 4*(precision == FP32) + log2(S) - 1, S = mps_slot_dim(...);
+ * S must not exceed MPS_MIXED_MAX_SLOT (MPS_ERR_CAPACITY from mps_plan_mixed otherwise). */
 #define MPS_MIXED_BUCKETS 8
 typedef struct {
   int32_t n_req;

@@ -21,7 +21,8 @@ PREC_FP64, PREC_FP32, PREC_SPLIT_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "split_bf16": PREC_SPLIT_BF16}
 LAYER_RYRZ_LADDER, LAYER_H_RY_BRICKWORK = 0, 1
 IMG_NONFINITE, IMG_NO_CONVERGENCE = 1, 2
-MAX_BOND = 16
+MAX_BOND = 128
+MIXED_MAX_SLOT = 16
 
 _lib = None
 

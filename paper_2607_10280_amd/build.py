@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libanomps.so")
-SOURCES = ["abi.hip", "layer.hip", "measure.hip", "measure_mfma.hip", "readout.hip", "train.hip"]
+SOURCES = ["abi.hip", "layer.hip", "measure.hip", "measure_mfma.hip", "readout.hip", "train.hip", "wide.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

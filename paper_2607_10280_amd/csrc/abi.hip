@@ -86,6 +86,9 @@ int check_request(const mps_request& r, int idx) {
   if (rc) return fail(rc, "request %d: %s", idx, g_last_error.c_str());
   if (r.precision == MPS_PREC_SPLIT_BF16)
     return fail(MPS_ERR_UNSUPPORTED, "request %d: split-bf16 requests are not built in this library", idx);
+  if (slot_bucket(r.n_sites, r.chi, r.n_layers) > kMaxBond)
+    return fail(MPS_ERR_CAPACITY, "request %d: slot %d exceeds the mixed-table limit %d", idx,
+                slot_bucket(r.n_sites, r.chi, r.n_layers), kMaxBond);
   if (r.n_pairs < 0 || r.reserved != 0)
     return fail(MPS_ERR_INVALID_ARG, "request %d: n_pairs=%d reserved=%d", idx, r.n_pairs, r.reserved);
   if (!r.pixels || !r.state || !r.env || !r.ctrl)
@@ -132,10 +135,23 @@ size_t mps_state_bytes(int32_t n, int32_t chi, int32_t layers, int32_t batch, in
   return (size_t)batch * n * 2 * S * S * 2 * real_size(prec);
 }
 
+// Environments [batch][2][n+1][S][S]; wide slots (S > kMaxBond) append a 256-byte aligned FP64
+// workspace of wide_workspace_bytes(S) per image, used by the layer and measurement kernels.
+size_t env_part_bytes(int n, int S, int batch, int prec) {
+  const size_t e = (size_t)batch * 2 * (n + 1) * S * S * 2 * real_size(prec);
+  return S > kMaxBond ? (e + 255) / 256 * 256 : e;
+}
+
+double* wide_ws(const mps_batch* b, int S) {
+  return (double*)((char*)b->env + env_part_bytes(b->n_sites, S, b->batch, b->precision));
+}
+
 size_t mps_env_bytes(int32_t n, int32_t chi, int32_t layers, int32_t batch, int32_t prec) {
   if (check_shape(n, chi, layers, batch, prec)) return 0;
-  const size_t S = slot_bucket(n, chi, layers);
-  return (size_t)batch * 2 * (n + 1) * S * S * 2 * real_size(prec);
+  const int S = slot_bucket(n, chi, layers);
+  size_t e = env_part_bytes(n, S, batch, prec);
+  if (S > kMaxBond) e += (size_t)batch * wide_workspace_bytes(S);
+  return e;
 }
 
 int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream) {
@@ -169,12 +185,23 @@ int mps_apply_layer_program(mps_batch* b, int32_t program, const double* theta,
     return fail(MPS_ERR_INVALID_ARG, "layers_done=%d: batch sized for %d layers", b->layers_done, b->n_layers);
   const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
   hipError_t e;
-  if (b->precision == MPS_PREC_FP64)
+  if (S > kMaxBond) {
+    if (!b->env) return fail(MPS_ERR_INVALID_ARG, "env is NULL (slot %d layers use it as workspace)", S);
+    if (b->precision == MPS_PREC_FP64)
+      e = launch_layer_wide<double>((double*)b->state, wide_ws(b, S), b->n_sites, b->chi, S,
+                                    b->layers_done, b->batch, program, theta, phi, pixels,
+                                    trunc_err, b->status, stream);
+    else
+      e = launch_layer_wide<float>((float*)b->state, wide_ws(b, S), b->n_sites, b->chi, S,
+                                   b->layers_done, b->batch, program, theta, phi, pixels,
+                                   trunc_err, b->status, stream);
+  } else if (b->precision == MPS_PREC_FP64) {
     e = launch_layer<double>((double*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
                              program, theta, phi, pixels, trunc_err, b->status, stream);
-  else
+  } else {
     e = launch_layer<float>((float*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
                             program, theta, phi, pixels, trunc_err, b->status, stream);
+  }
   if (e != hipSuccess) return check_hip(e, "layer launch");
   b->layers_done += 1;
   return ok();
@@ -224,7 +251,14 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
   const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
   const int L = b->layers_done;
   hipError_t e;
-  if (b->precision == MPS_PREC_FP64) {
+  if (S > kMaxBond) {
+    if (b->precision == MPS_PREC_FP64)
+      e = launch_measure_wide<double>((const double*)b->state, (double*)b->env, wide_ws(b, S), pairs,
+                                      m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
+    else
+      e = launch_measure_wide<float>((const float*)b->state, (float*)b->env, wide_ws(b, S), pairs,
+                                     m, b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
+  } else if (b->precision == MPS_PREC_FP64) {
     e = launch_envs<double, double>((const double*)b->state, (double*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)
       e = launch_pairs<double, double>((const double*)b->state, (const double*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);

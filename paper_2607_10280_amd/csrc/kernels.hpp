@@ -34,6 +34,19 @@ hipError_t launch_measure16(const float* state, float* env, const int* pairs, in
                             int chi, int layers, int batch, float* out, bool split_bf16,
                             hipStream_t stream);
 
+// Wide slots (S = 32, 64, 128; wide.hip): the same layer and measurement with one 256-lane
+// workgroup per image and the per-bond matrices in an FP64 workspace of
+// wide_workspace_bytes(S) bytes per image (placed by the library after the environments).
+size_t wide_workspace_bytes(int S);
+template <typename T>
+hipError_t launch_layer_wide(T* state, double* ws, int n, int chi, int S, int layer, int batch,
+                             int program, const double* theta, const double* phi,
+                             const double* pixels, double* trunc_err, int* status,
+                             hipStream_t stream);
+template <typename T>
+hipError_t launch_measure_wide(const T* state, T* env, double* ws, const int* pairs, int m, int n,
+                               int chi, int S, int layers, int batch, T* out, hipStream_t stream);
+
 // Mixed request tables: entries [begin, begin + count) form one bucket (slot S, precision T).
 template <typename T>
 hipError_t launch_encode_mixed(const mps_request* reqs, int begin, int count, int S,

@@ -50,11 +50,29 @@ def test_sizes():
     assert anomps.state_bytes(49, 16, 4, 1024, P) == 1024 * 49 * 2 * 16 * 16 * 2 * 4
     assert anomps.env_bytes(49, 16, 4, 1024, P) == 1024 * 2 * 50 * 16 * 16 * 2 * 4
     assert anomps.state_bytes(49, 16, 4, 2, anomps.PREC_FP64) == 2 * 49 * 2 * 256 * 2 * 8
-    # over capacity: bond 32 is beyond this build
-    assert anomps.state_bytes(49, 32, 5, 1, P) == 0
+    # over capacity: bond 256 is beyond this build (slots up to 128)
+    assert anomps.state_bytes(49, 256, 8, 1, P) == 0
     assert "MPS_MAX_BOND" in anomps.lib().mps_last_error().decode()
+    assert anomps.slot_dim(49, 128, 7) == 128 and anomps.slot_dim(16, 64, 6) == 64
     assert anomps.state_bytes(1, 4, 1, 1, P) == 0
     assert anomps.state_bytes(16, 4, 1, 1, 7) == 0
+
+
+def test_wide_slot_sizes():
+    """Slots beyond 16 append an FP64 workspace per image to the environment buffer: the larger of
+    the layer's 12 S^2, both environment sides' 6 S^2 and four pair workgroups' 4 x 12 S^2
+    complex128 elements, after the environments rounded up to 256 bytes."""
+    for n, chi, L, B, P, real in [(49, 32, 5, 3, anomps.PREC_FP32, 4), (16, 64, 6, 2, anomps.PREC_FP64, 8),
+                                  (49, 128, 7, 1, anomps.PREC_FP32, 4), (11, 32, 8, 5, anomps.PREC_FP32, 4)]:
+        S = anomps.slot_dim(n, chi, L)
+        assert S > 16
+        env = B * 2 * (n + 1) * S * S * 2 * real
+        env = (env + 255) // 256 * 256
+        ws = -(-48 * S * S // 64) * 64 * 16
+        assert anomps.env_bytes(n, chi, L, B, P) == env + B * ws
+        assert anomps.state_bytes(n, chi, L, B, P) == B * n * 2 * S * S * 2 * real
+    # narrow slots keep the plain environment size
+    assert anomps.env_bytes(49, 16, 4, 2, anomps.PREC_FP32) == 2 * 2 * 50 * 16 * 16 * 2 * 4
 
 
 def test_validate_pairs():
@@ -112,6 +130,6 @@ def test_plan_mixed_rejects_bad_requests():
     assert e.value.code == -4
     with pytest.raises(anomps.MpsError) as e:
         anomps.plan_mixed([_req(64, 32, 5, anomps.PREC_FP32)])
-    assert e.value.code == -2
+    assert e.value.code == -2 and "mixed-table limit" in str(e.value)
     order, plan = anomps.plan_mixed([])
     assert len(order) == 0 and plan.n_req == 0
