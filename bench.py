@@ -64,10 +64,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "mixed", "serve", "grid", "paper"],
+                    choices=["headline", "mixed", "serve", "grid", "paper", "chisweep"],
                     help="headline: the 7x7 L=4 chi=16 batch; mixed: 4096 requests of mixed size "
                          "and depth through the persistent mixed-table launches; serve: Poisson "
-                         "arrivals through the continuous-batching loop")
+                         "arrivals through the continuous-batching loop; chisweep: feature error "
+                         "and cost against chi at 7x7, L=7 (chi=128 is exact)")
     ap.add_argument("--requests", type=int, default=0, help="mixed/serve: number of requests")
     ap.add_argument("--tune-cache", default="", help="mixed/serve: autotuner JSON cache path")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -383,6 +384,73 @@ def run_paper(args):
         "status_nonzero": int(np.count_nonzero(b.status.cpu()))}))
 
 
+def run_chisweep(args):
+    """Accuracy and cost against the bond limit (the analogue of the paper's chi study, §III on
+    synthetic images): 7x7 blob images, L = 7 layers of the R_Y R_Z + CNOT-ladder circuit, chi in
+    2..128.  chi = 128 = 2^L keeps every Schmidt value, so it is the exact result; each cell
+    reports the mean and max feature error against it, the mean discarded weight per bond and
+    the batch time.  The exact reference is checked against the oracle on one image."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs
+    from oracle import features as ofeat
+    prec = anomps.PRECISIONS[args.precision]
+    p, L = args.p, 7
+    B = args.batch if args.batch != 1024 else 256
+    n = p * p
+    x = inputs.blob_images(B, p, 2)
+    th, ph = inputs.layer_angles(L, n, 11)
+    pairs = inputs.neighbour_pairs(p)
+    pd = torch.as_tensor(pairs, device="cuda")
+    pix = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    thd = torch.as_tensor(th, device="cuda").contiguous()
+    phd = torch.as_tensor(ph, device="cuda").contiguous()
+    real = torch.float64 if prec == anomps.PREC_FP64 else torch.float32
+
+    def run(chi, nb):
+        b = anomps.new_batch(n, chi, L, nb, prec)
+        out = torch.empty((nb, len(pairs), 15), dtype=real, device="cuda")
+        te = torch.zeros((L, nb, n - 1), dtype=torch.float64, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        anomps.init_batch(b, pix[:nb])
+        for layer in range(L):
+            anomps.apply_layer(b, thd[layer], phd[layer], te[layer])
+        anomps.pauli_pair_expect(b, pd, out)
+        e1.record()
+        torch.cuda.synchronize()
+        res = (out.double().cpu().numpy(), te.cpu().numpy(), int(np.count_nonzero(b.status.cpu())),
+               e0.elapsed_time(e1))
+        del b, out, te
+        return res
+
+    chis = (2, 4, 8, 16, 32, 64, 128)
+    results = {}
+    for chi in chis:
+        run(chi, 4)  # code and allocator warm-up
+        results[chi] = run(chi, B)
+        print(f"[chisweep] chi={chi} {results[chi][3]:.1f} ms", file=sys.stderr, flush=True)
+    ref = results[128][0]
+    oracle_ref = ofeat.exact_features(x[:1], th, ph, pairs)
+    cells = []
+    for chi in chis:
+        o, te, bad, ms = results[chi]
+        err = np.abs(o - ref)
+        cells.append({"chi": chi, "slot": anomps.slot_dim(n, chi, L), "ms": round(ms, 2),
+                      "images_per_s": round(B / (ms * 1e-3), 1),
+                      "mae": float(err.mean()), "max_abs_err": float(err.max()),
+                      "mean_discarded_weight_per_bond": float(te.sum(axis=0).mean()),
+                      "status_nonzero": bad})
+    print(json.dumps({
+        "metric": "feature error and cost against chi, 7x7, L=7 (chi=128 exact)",
+        "value": cells[-1]["images_per_s"], "unit": "images/s (chi=128 cell)", "n_gpus": 1,
+        "steps": 1, "higher_is_better": True, "data": "synthetic",
+        "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision,
+        "config": {"workload": f"{p}x{p} Gaussian blobs, R_Y R_Z + CNOT ladder, L={L}, "
+                               f"{len(pairs)} H+V pairs", "global_batch": B},
+        "reference_vs_oracle_max_abs_err": float(np.abs(ref[:1] - oracle_ref).max()),
+        "cells": cells}))
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     args = parse()
@@ -397,6 +465,8 @@ def main():
         return run_grid(args)
     if args.workload == "paper":
         return run_paper(args)
+    if args.workload == "chisweep":
+        return run_chisweep(args)
     import torch
     from paper_2607_10280_amd import anomps, inputs, workload
 
