@@ -566,13 +566,33 @@ def main():
             lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat)
 
+    # The same batch with every layer through the canonical sweep + Jacobi SVD ladder (the
+    # default splits layers that keep every singular value by QR in one sweep).
+    anomps.set_exact_layers(anomps.EXACT_SVD)
+    try:
+        step()
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(args.steps):
+            step()
+        s1.record()
+        torch.cuda.synchronize()
+        svd_ms = s0.elapsed_time(s1) / args.steps
+        svd_err = float(np.abs(out_d.cpu().numpy().astype(np.float64) - gpu_out).max())
+    finally:
+        anomps.set_exact_layers(anomps.EXACT_QR)
+    qr_layers = [l for l in range(L) if workload.layer_keeps_all(n, chi, l)]
+
     # Roofline of the dominant kernel family.
     lay_flops = sum(workload.layer_flops(n, chi, l)["total_fp64"] for l in range(L)) * B
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
     mfma = prec == anomps.PREC_FP32 and anomps.slot_dim(n, chi, L) == 16
     cand = {
         "layer": (lay_flops / L, avg["layer"], "alu", PEAK_FP64_TFLOPS,
-                  "FP64 VALU: Jacobi SVD + canonical sweep, per layer launch (nominal R-SVD count)"),
+                  "FP64 VALU, per layer launch: Householder QR split + contractions for layers "
+                  "that keep every singular value, else Jacobi SVD (nominal R-SVD count) + "
+                  "canonical sweep"),
         "measure": (meas_flops, avg["measure"], "mfma" if mfma else "alu",
                     PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else
                     (PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS),
@@ -614,6 +634,9 @@ def main():
         "batched_latency_ms": round(ms_per_step, 4),
         "status_nonzero": int(np.count_nonzero(status)),
         "roofline": roofline,
+        "exact_layers": {"qr_split_layers": qr_layers, "svd_every_layer": {
+            "images_per_s": round(B / (svd_ms * 1e-3), 1), "ms_per_step": round(svd_ms, 4),
+            "max_abs_diff_vs_qr": svd_err}},
     }
     if not args.no_cpu_baseline:
         ref, cpu = cpu_baseline(x, th, ph, pairs, chi, min(args.cpu_sample, B))

@@ -147,6 +147,24 @@ int mps_init_batch(mps_batch* b, const double* pixels, hipStream_t stream);
 int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double* trunc_err,
                     hipStream_t stream);
 
+/*
+ * How mps_apply_layer (and the mixed layer step) split the bonds of a layer in which the bond
+ * rule keeps every singular value, i.e. D_k = min(2 D_{k-1}, 2 D_{k+1}^old) at every bond k
+ * (always the case when chi >= 2^n_layers, the exact regime of §II-B):
+ *  MPS_EXACT_QR (default): one left-to-right sweep; each two-site matrix Theta' is split
+ *    exactly, by Householder QR in FP64 (A[k] <- Q, centre <- R) or, when D_k equals its row
+ *    count, as A[k] <- identity, centre <- Theta'; the one-qubit gates are applied as each
+ *    site is reached, the last centre is scaled to unit norm, and trunc_err is 0.  Nothing can
+ *    be discarded in such a layer, so the state is the one the SVD ladder produces (up to
+ *    rounding and the gauge of each bond) and the features agree to rounding.
+ *  MPS_EXACT_SVD: the canonical sweep + Jacobi SVD ladder, as for every other layer.
+ * Layers with any truncating bond, the H-R_Y brickwork program and slots wider than 16 always
+ * use the canonical sweep + SVD.  Process-wide setting, read at each launch.  Returns
+ * MPS_ERR_INVALID_ARG for another mode.
+ */
+enum { MPS_EXACT_QR = 0, MPS_EXACT_SVD = 1 };
+int mps_set_exact_layers(int32_t mode);
+
 /* Layer programs of mps_apply_layer_program. */
 enum {
   MPS_LAYER_RYRZ_LADDER = 0,    /* R_Y(theta_k) R_Z(phi_k), then the CNOT ladder (mps_apply_layer) */

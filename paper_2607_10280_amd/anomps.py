@@ -106,6 +106,7 @@ EXPORTS = {
     "mps_pauli_pair_expect_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan),
                                                    ctypes.c_void_p]),
     "mps_set_mixed_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "mps_set_exact_layers": (ctypes.c_int, [ctypes.c_int32]),
     "mps_ano_train_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 4),
     "mps_ano_train_step": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_int32] * 4 +
                            [ctypes.c_double] * 5 + [ctypes.c_void_p, ctypes.c_void_p,
@@ -369,6 +370,15 @@ def apply_layer_mixed(table, plan: MixedPlan, queue, stream=None) -> None:
 
 def pauli_pair_expect_mixed(table, plan: MixedPlan, stream=None) -> None:
     _check(lib().mps_pauli_pair_expect_mixed(_ptr(table), ctypes.byref(plan), _stream(stream)))
+
+
+EXACT_QR, EXACT_SVD = 0, 1
+
+
+def set_exact_layers(mode: int) -> None:
+    """EXACT_QR (default): ladder layers that keep every singular value are split by QR in one
+    sweep; EXACT_SVD: canonical sweep + Jacobi SVD for every layer."""
+    _check(lib().mps_set_exact_layers(mode))
 
 
 def set_mixed_tuning(bucket: int, blocks_per_cu: int) -> None:

@@ -388,6 +388,12 @@ int mps_pauli_pair_expect_mixed(const mps_request* reqs, const mps_mixed_plan* p
   return ok();
 }
 
+int mps_set_exact_layers(int32_t mode) {
+  if (mode != MPS_EXACT_QR && mode != MPS_EXACT_SVD) return fail(MPS_ERR_INVALID_ARG, "mode=%d", mode);
+  set_exact_qr(mode == MPS_EXACT_QR);
+  return ok();
+}
+
 int mps_set_mixed_tuning(int32_t bucket, int32_t blocks_per_cu) {
   if (bucket < 0 || bucket >= MPS_MIXED_BUCKETS || blocks_per_cu < 0)
     return fail(MPS_ERR_INVALID_ARG, "bucket=%d blocks_per_cu=%d", bucket, blocks_per_cu);

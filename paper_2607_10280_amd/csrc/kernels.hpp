@@ -18,6 +18,11 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
                         const double* theta, const double* phi, const double* pixels,
                         double* trunc_err, int* status, hipStream_t stream);
 
+// Ladder layers in which every bond keeps all its singular values: split by Householder QR in
+// one sweep (on, the default) or by the canonical sweep + Jacobi SVD ladder (off).
+void set_exact_qr(int on);
+int exact_qr();
+
 // Environment sweeps (left and right) and pair expectations.  T = storage type of the state,
 // C = compute/output type of the measurement (double for FP64 batches, float otherwise).
 template <typename T, typename C>

@@ -261,9 +261,11 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
 // every later column takes the reflection.  A column whose remaining part has |.|^2 <= 1e-30
 // |A|_F^2 is left as it is (H_j = I).  Q is then formed by applying H_{N-1}, ..., H_0 to the
 // first N unit vectors.
-// Out: uq[j*SP + a] = L[j][a]; rows of Q conjugated into the site slot as [a][s][b] (row index
-// r = s*Dr + b).
-template <int S, typename T, int NC, int R>
+// Out: uq[j*SP + a] = L[j][a] = conj(R[a][j]).  LADDER = false (canonical sweep): rows of Q
+// conjugated into the site slot as [a][s][b] (row index r = s*Dr + b).  LADDER = true (a
+// two-site matrix Theta = Q R split without truncation): Q itself into the slot as
+// [(a,s)][j], row index r = a*2 + s, column j.
+template <int S, typename T, int NC, int R, bool LADDER>
 __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
@@ -359,14 +361,18 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
       x[t].im -= gr * v[t].im + gi * v[t].re;
     }
   }
-  // Row c of Q = conj(column c of the product).
   if (own) {
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       const int rr = lt + t * TM;
       if (rr < M) {
-        const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
-        store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(x[t]));
+        if constexpr (LADDER) {
+          store_c<T, double>(slot, (size_t)rr * S + c, x[t]);  // Q[rr][c]
+        } else {
+          // row c of Q = conj(column c of the product)
+          const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
+          store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(x[t]));
+        }
       }
     }
   }
@@ -379,14 +385,14 @@ __host__ __device__ inline int lq_rows_per_lane(int M, int N) {
   return pow2ceil((M + tm - 1) / tm);
 }
 
-template <int S, typename T>
+template <int S, typename T, bool LADDER>
 __device__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
   const int nc = pow2ceil(N < 1 ? 1 : N), r = lq_rows_per_lane(M, N);
 #define ANOMPS_LQ(NCV, RV)                                                                  \
   if (nc == NCV && r == RV) {                                                              \
     if constexpr (NCV <= S && RV * ((kLayerThreads / NCV) < 16 ? kLayerThreads / NCV : 16) <= \
                                   LayerShared<S, T>::LD) {                                 \
-      householder_lq<S, T, NCV, RV>(sh, M, N, Dr, slot);                                   \
+      householder_lq<S, T, NCV, RV, LADDER>(sh, M, N, Dr, slot);                           \
       return 0;                                                                            \
     }                                                                                      \
   }
@@ -527,7 +533,7 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
     }
     __syncthreads();
     // t = L Q: Q (right-canonical rows) goes to site k, L to uq.
-    flags |= lq_columns<S, T>(sh, M, N, Dr, st + (size_t)k * SLOT);
+    flags |= lq_columns<S, T, false>(sh, M, N, Dr, st + (size_t)k * SLOT);
     pf.commit(sh.tb);
     __syncthreads();
     const FastDiv fdl(Dl);
@@ -652,6 +658,116 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
   return flags;
 }
 
+// True when layer `layer` of the CNOT-ladder circuit keeps every singular value at every bond:
+// the bond rule gives D_k = min(rows, cols) of each two-site matrix, so no weight can be
+// discarded and the split of each bond is exact whatever factorisation is used.
+__device__ __forceinline__ bool layer_keeps_all(int n, int chi, int layer) {
+  for (int k = 0; k <= n - 2; ++k) {
+    const int M = 2 * bond_dim(n, chi, layer + 1, k - 1), N = 2 * bond_dim(n, chi, layer, k + 1);
+    if (bond_dim(n, chi, layer + 1, k) != (M < N ? M : N)) return false;
+  }
+  return true;
+}
+
+// A ladder layer without truncation (layer_keeps_all): one left-to-right sweep.  Site 0 takes
+// its gate in FP64, then for each bond k the gated neighbour U_{k+1} A[k+1] (the gate commutes
+// with the CNOTs on the bonds to its left) is contracted with the centre into
+// Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] (U A[k+1])[c, t XOR s, b] and split exactly: when
+// D = rows, A[k] <- the identity and the centre <- Theta'; when D = cols (< rows),
+// Theta' = Q R by Householder, A[k] <- Q and the centre <- R.  Every A[k] is left-orthonormal,
+// no canonical sweep is needed, the discarded weight of each bond is 0, and the last centre is
+// scaled to unit norm.  The state equals the one the canonical sweep + SVD ladder produces,
+// up to rounding and the gauge of each bond.
+template <int S, typename T, typename Before, typename After>
+__device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Before before,
+                                        After after, const double* theta, const double* phi,
+                                        double* trunc_err, SitePrefetch<S, T>& pf) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  const int tid = threadIdx.x;
+  int flags = 0;
+  pf.load(st, 1, before(0));
+  pf.commit(sh.tb);
+  __syncthreads();
+  pf.load(st + SLOT, before(0), before(1));
+  for (int idx = tid; idx < 2 * before(0); idx += kLayerThreads) {
+    const int s_ = idx / before(0), c = idx - s_ * before(0);
+    sh.ta[s_ * SP + c] = to_cd(sh.tb[s_ * SP + c]);
+  }
+  __syncthreads();
+  apply_gate<S, T>(sh, 1, before(0), site_gate(kGateRyRz, 0, theta, phi, nullptr));
+  for (int k = 0; k <= n - 2; ++k) {
+    const int Dl = after(k - 1), Dc = before(k), Dr = before(k + 1), D = after(k);
+    pf.commit(sh.tb);
+    __syncthreads();
+    if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
+    // gated neighbour in FP64: uq[(c*2 + t)*SP + b]
+    {
+      const Gate2 g = site_gate(kGateRyRz, k + 1, theta, phi, nullptr);
+      const FastDiv fdr(Dr);
+      for (int idx = tid; idx < Dc * Dr; idx += kLayerThreads) {
+        const int c = fdr.q(idx), b = fdr.r(idx);
+        const cd v0 = to_cd(sh.tb[(c * 2) * SP + b]), v1 = to_cd(sh.tb[(c * 2 + 1) * SP + b]);
+        cd w0 = cmul(g.u00, v0), w1 = cmul(g.u10, v0);
+        cfma(w0, g.u01, v1);
+        cfma(w1, g.u11, v1);
+        sh.uq[(c * 2) * SP + b] = w0;
+        sh.uq[(c * 2 + 1) * SP + b] = w1;
+      }
+    }
+    __syncthreads();
+    const int M = 2 * Dl, N = 2 * Dr;
+    {
+      const FastDiv fm(M), fdr(Dr);
+      for (int idx = tid; idx < N * M; idx += kLayerThreads) {
+        const int col = fm.q(idx), row = fm.r(idx);
+        const int t = col >= Dr, b = col - (t ? Dr : 0), s_ = row & 1;
+        cd acc{0.0, 0.0};
+        for (int c = 0; c < Dc; ++c) cfma(acc, sh.ta[row * SP + c], sh.uq[(c * 2 + (t ^ s_)) * SP + b]);
+        sh.mat[col * LD + row] = acc;
+      }
+    }
+    __syncthreads();
+    T* slot = st + (size_t)k * SLOT;
+    const FastDiv fn(N);
+    if (D == M) {
+      const FastDiv fmm(M);
+      for (int idx = tid; idx < M * M; idx += kLayerThreads) {
+        const int row = fmm.q(idx), j = fmm.r(idx);
+        store_c<T, double>(slot, (size_t)row * S + j, cd{row == j ? 1.0 : 0.0, 0.0});
+      }
+      for (int idx = tid; idx < D * N; idx += kLayerThreads) {
+        const int j = fn.q(idx), col = fn.r(idx);
+        const int t = col >= Dr, b = col - (t ? Dr : 0);
+        sh.ta[(j * 2 + t) * SP + b] = sh.mat[col * LD + j];
+      }
+    } else {
+      flags |= lq_columns<S, T, true>(sh, M, N, Dr, slot);
+      for (int idx = tid; idx < D * N; idx += kLayerThreads) {
+        const int j = fn.q(idx), col = fn.r(idx);
+        const int t = col >= Dr, b = col - (t ? Dr : 0);
+        sh.ta[(j * 2 + t) * SP + b] = j <= col ? cconj(sh.uq[col * SP + j]) : cd{0.0, 0.0};
+      }
+    }
+    if (tid == 0 && trunc_err) trunc_err[k] = 0.0;
+    __syncthreads();
+  }
+  const int Dn = after(n - 2);
+  double f = 0.0;
+  for (int idx = tid; idx < 2 * Dn; idx += kLayerThreads) {
+    const cd v = sh.ta[idx * SP];
+    f = fma(v.re, v.re, fma(v.im, v.im, f));
+  }
+  f = block_sum(f, sh.red);
+  if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
+  const double scale = f > 0.0 ? rsqrt_full(f) : 0.0;
+  for (int idx = tid; idx < 2 * Dn; idx += kLayerThreads) sh.ta[idx * SP] = cscale(sh.ta[idx * SP], scale);
+  __syncthreads();
+  store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, Dn, 1);
+  return flags;
+}
+
 // Applies layer `layer` (0-based) to one image whose n slots start at `st`.
 //  program kLayerRyRzLadder: R_Y(theta_k) R_Z(phi_k) on every site, then CNOT(k, k+1) for
 //    k = 0..n-2 in order: one canonical sweep and one CNOT sweep.
@@ -664,7 +780,8 @@ enum : int { kLayerRyRzLadder = 0, kLayerHRyBrickwork = 1 };
 template <int S, typename T>
 __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
                                             int program, const double* theta, const double* phi,
-                                            const double* pix, double* trunc_err, int* status) {
+                                            const double* pix, double* trunc_err, int* status,
+                                            int exact_qr) {
   auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
   auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
   SitePrefetch<S, T> pf;
@@ -675,6 +792,8 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     flags |= cnot_sweep<S, T>(sh, st, n, dold, dmid, 0, trunc_err, pf);
     flags |= canon_sweep<S, T>(sh, st, n, dmid, kGateNone, theta, phi, pix, true, pf);
     flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf);
+  } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
+    flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
   } else {
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateRyRz, theta, phi, pix, false, pf);
     flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf);
@@ -687,14 +806,21 @@ template <int S, typename T, int PROG>
 __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int chi, int layer,
                                                          const double* theta, const double* phi,
                                                          const double* pixels, double* trunc_err,
-                                                         int* status) {
+                                                         int* status, int exact_qr) {
   __shared__ LayerShared<S, T> sh;
   const int b = blockIdx.x;
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
   layer_chain<S, T>(sh, st, n, chi, layer, PROG, theta, phi,
                     pixels ? pixels + (size_t)b * n : nullptr,
-                    trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b);
+                    trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b, exact_qr);
 }
+
+// Host-side policy for ladder layers that keep every singular value (1: QR sweep, 0: canonical
+// sweep + Jacobi SVD ladder like every other layer), read at each launch.
+int g_exact_qr = 1;
+
+void set_exact_qr(int on) { g_exact_qr = on ? 1 : 0; }
+int exact_qr() { return g_exact_qr; }
 
 // ------------------------------------------------------------------------------- mixed requests
 // Encode: one workgroup per request of the bucket (same arithmetic as k_encode).
@@ -732,7 +858,8 @@ __global__ void k_encode_mixed(const mps_request* reqs, int begin, int S) {
 // their readfirstlane to a constant, after which those lanes never see the queue advance.
 template <int S, typename T>
 __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request* reqs, int begin,
-                                                               int count, int* queue) {
+                                                               int count, int* queue,
+                                                               int exact_qr) {
   __shared__ LayerShared<S, T> sh;
   for (;;) {
     const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
@@ -747,7 +874,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request
     const double* phi = uniform_ptr(r->phi) + (size_t)layer * n;
     double* te = uniform_ptr(r->trunc_err);
     layer_chain<S, T>(sh, uniform_ptr((T*)r->state), n, chi, layer, kLayerRyRzLadder, theta, phi,
-                      nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1);
+                      nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1, exact_qr);
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = layer + 1;
   }
@@ -804,7 +931,7 @@ hipError_t launch_layer_mixed_s(const mps_request* reqs, int begin, int count, i
   long long grid = (long long)per_cu * device_cus();
   if (grid > count) grid = count;
   hipLaunchKernelGGL((k_layer_mixed<S, T>), dim3((unsigned)grid), dim3(kLayerThreads), 0, stream,
-                     reqs, begin, count, queue);
+                     reqs, begin, count, queue, g_exact_qr);
   return hipGetLastError();
 }
 }  // namespace
@@ -840,10 +967,10 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
   case SV:                                                                                         \
     if (program == kLayerHRyBrickwork)                                                             \
       hipLaunchKernelGGL((k_layer<SV, T, kLayerHRyBrickwork>), grid, block, 0, stream, state, n,   \
-                         chi, layer, theta, phi, pixels, trunc_err, status);                       \
+                         chi, layer, theta, phi, pixels, trunc_err, status, g_exact_qr);           \
     else                                                                                           \
       hipLaunchKernelGGL((k_layer<SV, T, kLayerRyRzLadder>), grid, block, 0, stream, state, n,     \
-                         chi, layer, theta, phi, pixels, trunc_err, status);                       \
+                         chi, layer, theta, phi, pixels, trunc_err, status, g_exact_qr);           \
     break;
     ANOMPS_KL(2) ANOMPS_KL(4) ANOMPS_KL(8) ANOMPS_KL(16)
 #undef ANOMPS_KL

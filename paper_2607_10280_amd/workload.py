@@ -26,12 +26,38 @@ def svd_flops(m: int, n: int) -> float:
     return 4.0 * (6.0 * m * n * n + 20.0 * n ** 3)
 
 
-def layer_flops(n: int, chi: int, layer: int) -> dict:
-    """Work of applying layer `layer` (0-based) to one image: canonical sweep (gate + SVD of
-    each site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left neighbour), then the
-    ladder (two-site contraction, SVD, U^H Theta' for the new centre)."""
+def layer_keeps_all(n: int, chi: int, layer: int) -> bool:
+    """True when every bond of the layer keeps all min(rows, cols) singular values."""
+    return all(bond(n, chi, layer + 1, k) == min(2 * bond(n, chi, layer + 1, k - 1),
+                                                 2 * bond(n, chi, layer, k + 1))
+               for k in range(n - 1))
+
+
+def householder_qr_flops(m: int, n: int) -> float:
+    """Complex Householder QR of an m x n matrix (m >= n) with Q formed explicitly: each
+    reflector costs a dot product and an update over the remaining columns and rows, once to
+    reduce and once to form Q."""
+    return CMAC * 4.0 * sum((n - j) * (m - j) for j in range(n))
+
+
+def layer_flops(n: int, chi: int, layer: int, exact_qr: bool = True) -> dict:
+    """Work of applying layer `layer` (0-based) to one image.  A layer that keeps every singular
+    value (and exact_qr) is one sweep: gate the neighbour, contract Theta', split it by
+    Householder QR (or not at all when D equals its row count).  Otherwise: canonical sweep
+    (gate + SVD of each site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left
+    neighbour), then the ladder (two-site contraction, SVD, U^H Theta' for the new centre)."""
     d_old = lambda k: bond(n, chi, layer, k)
     d_new = lambda k: bond(n, chi, layer + 1, k)
+    if exact_qr and layer_keeps_all(n, chi, layer):
+        qr = other = 0.0
+        other += CMAC * 4 * d_old(0)
+        for k in range(n - 1):
+            dl, dc, dr, d = d_new(k - 1), d_old(k), d_old(k + 1), d_new(k)
+            rows, cols = 2 * dl, 2 * dr
+            other += CMAC * (4 * dc * dr + rows * cols * dc)
+            if d != rows:
+                qr += householder_qr_flops(rows, cols)
+        return {"qr_fp64": qr, "svd_fp64": 0.0, "other_fp64": other, "total_fp64": qr + other}
     svd = other = 0.0
     for k in range(n - 1, 0, -1):
         dl, dr = d_old(k - 1), d_old(k)
@@ -80,7 +106,10 @@ def state_bytes(n: int, chi: int, layers: int, real_bytes: int) -> int:
                for k in range(n))
 
 
-def layer_bytes(n: int, chi: int, layer: int, real_bytes: int) -> int:
+def layer_bytes(n: int, chi: int, layer: int, real_bytes: int, exact_qr: bool = True) -> int:
     """HBM traffic of one layer for one image: the canonical sweep reads and writes every
-    tensor once, the ladder reads and writes every tensor once."""
+    tensor once, the ladder reads and writes every tensor once; a layer split by QR in one sweep
+    reads the old tensors once and writes the new ones once."""
+    if exact_qr and layer_keeps_all(n, chi, layer):
+        return state_bytes(n, chi, layer, real_bytes) + state_bytes(n, chi, layer + 1, real_bytes)
     return 2 * state_bytes(n, chi, layer, real_bytes) + 2 * state_bytes(n, chi, layer + 1, real_bytes)

@@ -75,6 +75,14 @@ def test_wide_slot_sizes():
     assert anomps.env_bytes(49, 16, 4, 2, anomps.PREC_FP32) == 2 * 2 * 50 * 16 * 16 * 2 * 4
 
 
+def test_exact_layer_policy_arguments():
+    anomps.set_exact_layers(anomps.EXACT_SVD)
+    anomps.set_exact_layers(anomps.EXACT_QR)
+    with pytest.raises(anomps.MpsError) as e:
+        anomps.set_exact_layers(2)
+    assert e.value.code == -1
+
+
 def test_validate_pairs():
     anomps.validate_pairs(inputs.neighbour_pairs(7), 49)
     anomps.validate_pairs(np.zeros((0, 2), np.int32), 49)
