@@ -557,7 +557,7 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
 template <int S, typename T, typename Before, typename After>
 __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, Before before,
                                           After after, int parity, double* trunc_err,
-                                          SitePrefetch<S, T>& pf) {
+                                          SitePrefetch<S, T>& pf, int exact_qr) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
@@ -586,6 +586,22 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
       }
     }
     __syncthreads();
+    if (exact_qr && D == (M < N ? M : N)) {
+      // The bond keeps every singular value: the split needs no SVD (the centre is in canonical
+      // position, so the kept weight is |Theta'|_F^2 and the discarded weight is 0).
+      double f = 0.0;
+      const FastDiv fm(M);
+      for (int idx = tid; idx < N * M; idx += kLayerThreads) {
+        const cd v = sh.mat[fm.q(idx) * LD + fm.r(idx)];
+        f = fma(v.re, v.re, fma(v.im, v.im, f));
+      }
+      f = block_sum(f, sh.red);
+      if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
+      if (cx && tid == 0 && trunc_err) trunc_err[k] = 0.0;
+      flags |= exact_split<S, T>(sh, st + (size_t)k * SLOT, M, N, D, Dr, f > 0.0 ? rsqrt_full(f) : 0.0);
+      __syncthreads();
+      continue;
+    }
     flags |= jacobi_columns<S, T>(sh, M, N);
     const double tiny2 = sh.tiny2;
     // Rank columns by singular value (descending, ties by index; NaN counts as zero); thread c
@@ -655,6 +671,40 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
     __syncthreads();
   }
   store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, after(n - 2), 1);
+  return flags;
+}
+
+// Exact split of a two-site matrix Theta' (mat, M x N, column index t*Dr + b) that keeps all its
+// D = min(M, N) singular values: when D = M, A[k] <- the identity and the centre <- Theta';
+// otherwise (D = N < M) Theta' = Q R by Householder, A[k] <- Q and the centre <- R.  The
+// centre (ta, [j][t][b]) is multiplied by `scale`.
+template <int S, typename T>
+__device__ __forceinline__ int exact_split(LayerShared<S, T>& sh, T* slot, int M, int N, int D,
+                                           int Dr, double scale) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x;
+  int flags = 0;
+  const FastDiv fn(N);
+  if (D == M) {
+    const FastDiv fmm(M);
+    for (int idx = tid; idx < M * M; idx += kLayerThreads) {
+      const int row = fmm.q(idx), j = fmm.r(idx);
+      store_c<T, double>(slot, (size_t)row * S + j, cd{row == j ? 1.0 : 0.0, 0.0});
+    }
+    for (int idx = tid; idx < D * N; idx += kLayerThreads) {
+      const int j = fn.q(idx), col = fn.r(idx);
+      const int t = col >= Dr, b = col - (t ? Dr : 0);
+      sh.ta[(j * 2 + t) * SP + b] = cscale(sh.mat[col * LD + j], scale);
+    }
+  } else {
+    flags |= lq_columns<S, T, true>(sh, M, N, Dr, slot);
+    for (int idx = tid; idx < D * N; idx += kLayerThreads) {
+      const int j = fn.q(idx), col = fn.r(idx);
+      const int t = col >= Dr, b = col - (t ? Dr : 0);
+      sh.ta[(j * 2 + t) * SP + b] = j <= col ? cscale(cconj(sh.uq[col * SP + j]), scale) : cd{0.0, 0.0};
+    }
+  }
   return flags;
 }
 
@@ -729,27 +779,7 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
       }
     }
     __syncthreads();
-    T* slot = st + (size_t)k * SLOT;
-    const FastDiv fn(N);
-    if (D == M) {
-      const FastDiv fmm(M);
-      for (int idx = tid; idx < M * M; idx += kLayerThreads) {
-        const int row = fmm.q(idx), j = fmm.r(idx);
-        store_c<T, double>(slot, (size_t)row * S + j, cd{row == j ? 1.0 : 0.0, 0.0});
-      }
-      for (int idx = tid; idx < D * N; idx += kLayerThreads) {
-        const int j = fn.q(idx), col = fn.r(idx);
-        const int t = col >= Dr, b = col - (t ? Dr : 0);
-        sh.ta[(j * 2 + t) * SP + b] = sh.mat[col * LD + j];
-      }
-    } else {
-      flags |= lq_columns<S, T, true>(sh, M, N, Dr, slot);
-      for (int idx = tid; idx < D * N; idx += kLayerThreads) {
-        const int j = fn.q(idx), col = fn.r(idx);
-        const int t = col >= Dr, b = col - (t ? Dr : 0);
-        sh.ta[(j * 2 + t) * SP + b] = j <= col ? cconj(sh.uq[col * SP + j]) : cd{0.0, 0.0};
-      }
-    }
+    flags |= exact_split<S, T>(sh, st + (size_t)k * SLOT, M, N, D, Dr, 1.0);
     if (tid == 0 && trunc_err) trunc_err[k] = 0.0;
     __syncthreads();
   }
@@ -789,14 +819,14 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
   if (program == kLayerHRyBrickwork) {
     auto dmid = [&](int k) { return bond_dim(n, chi, (k & 1) ? layer : layer + 1, k); };
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateHRy, theta, phi, pix, false, pf);
-    flags |= cnot_sweep<S, T>(sh, st, n, dold, dmid, 0, trunc_err, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dold, dmid, 0, trunc_err, pf, exact_qr);
     flags |= canon_sweep<S, T>(sh, st, n, dmid, kGateNone, theta, phi, pix, true, pf);
-    flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf, exact_qr);
   } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
     flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
   } else {
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateRyRz, theta, phi, pix, false, pf);
-    flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf);
+    flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf, exact_qr);
   }
   if (threadIdx.x == 0 && flags) status[0] |= flags;
 }
