@@ -158,9 +158,11 @@ int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double
  *    be discarded in such a layer, so the state is the one the SVD ladder produces (up to
  *    rounding and the gauge of each bond) and the features agree to rounding.
  *  MPS_EXACT_SVD: the canonical sweep + Jacobi SVD ladder, as for every other layer.
- * Layers with any truncating bond, the H-R_Y brickwork program and slots wider than 16 always
- * use the canonical sweep + SVD.  Process-wide setting, read at each launch.  Returns
- * MPS_ERR_INVALID_ARG for another mode.
+ * Layers with any truncating bond, the H-R_Y brickwork program and slots wider than 16 keep the
+ * canonical sweep; under MPS_EXACT_QR their ladder still splits each bond that keeps all
+ * min(rows, cols) singular values exactly (identity or QR, centre renormalised by |Theta'|)
+ * and runs the Jacobi SVD only where weight can be discarded.  Process-wide setting, read at
+ * each launch.  Returns MPS_ERR_INVALID_ARG for another mode.
  */
 enum { MPS_EXACT_QR = 0, MPS_EXACT_SVD = 1 };
 int mps_set_exact_layers(int32_t mode);

@@ -166,7 +166,8 @@ __device__ void wapply_gate(cd* ta, int S, int Dl, int Dr, int mode, int k, cons
 // columns (H_0 ... H_{N-1} applied to e_c) are formed in w.xb; Q's rows, conjugated, go to the
 // site slot, and L to w.uq[j*S + a].
 template <typename T>
-__device__ void wide_lq(WideShared& sh, const WideWs& w, int S, int M, int N, int Dr, T* slot) {
+__device__ void wide_lq(WideShared& sh, const WideWs& w, int S, int M, int N, int Dr, T* slot,
+                        bool ladder = false) {
   const int ld = 2 * S;
   const int tid = threadIdx.x, team = tid / kTeam, lt = tid % kTeam;
   double f = 0.0;
@@ -249,10 +250,17 @@ __device__ void wide_lq(WideShared& sh, const WideWs& w, int S, int M, int N, in
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < N * M; idx += kWT) {
-    const int c = idx / M, r = idx % M;
-    const int s_ = r >= Dr, b = r - (s_ ? Dr : 0);
-    store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(w.xb[(size_t)c * ld + r]));
+  if (ladder) {  // Theta' = Q R: Q itself into the slot as [(a,s)][j], row r = a*2 + s
+    for (int idx = tid; idx < N * M; idx += kWT) {
+      const int r = idx / N, c = idx % N;
+      store_c<T, double>(slot, (size_t)r * S + c, w.xb[(size_t)c * ld + r]);
+    }
+  } else {
+    for (int idx = tid; idx < N * M; idx += kWT) {
+      const int c = idx / M, r = idx % M;
+      const int s_ = r >= Dr, b = r - (s_ ? Dr : 0);
+      store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(w.xb[(size_t)c * ld + r]));
+    }
   }
   __syncthreads();
 }
@@ -393,7 +401,7 @@ __device__ int wide_canon(WideShared& sh, const WideWs& w, T* st, int S, int n, 
 // weight to one, records the discarded weight of CNOT bonds in trunc_err[k].
 template <typename T, typename Before, typename After>
 __device__ int wide_cnot(WideShared& sh, const WideWs& w, T* st, int S, int n, Before before,
-                         After after, int parity, double* trunc_err) {
+                         After after, int parity, double* trunc_err, int exact_qr) {
   const size_t SLOT = (size_t)2 * S * S * 2;
   const int ld = 2 * S, tid = threadIdx.x;
   int flags = 0;
@@ -413,6 +421,41 @@ __device__ int wide_cnot(WideShared& sh, const WideWs& w, T* st, int S, int n, B
       w.mat[(size_t)col * ld + row] = acc;
     }
     __syncthreads();
+    if (exact_qr && D == (M < N ? M : N)) {
+      // The bond keeps every singular value: split exactly (identity when D = M, else
+      // Householder QR), centre scaled by 1/|Theta'|_F, discarded weight 0.
+      double f = 0.0;
+      for (int idx = tid; idx < N * M; idx += kWT) {
+        const cd v = w.mat[(size_t)(idx / M) * ld + idx % M];
+        f = fma(v.re, v.re, fma(v.im, v.im, f));
+      }
+      f = wblock_sum(f, sh);
+      if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
+      const double scale = f > 0.0 ? w_rsqrt(f) : 0.0;
+      if (cx && tid == 0 && trunc_err) trunc_err[k] = 0.0;
+      T* slot = st + (size_t)k * SLOT;
+      if (D == M) {
+        for (int idx = tid; idx < M * M; idx += kWT) {
+          const int r = idx / M, j = idx % M;
+          store_c<T, double>(slot, (size_t)r * S + j, cd{r == j ? 1.0 : 0.0, 0.0});
+        }
+        for (int idx = tid; idx < D * N; idx += kWT) {
+          const int j = idx / N, col = idx % N;
+          const int t = col >= Dr, b = col - (t ? Dr : 0);
+          w.ta[(size_t)(j * 2 + t) * S + b] = cscale(w.mat[(size_t)col * ld + j], scale);
+        }
+      } else {
+        wide_lq(sh, w, S, M, N, Dr, slot, true);
+        for (int idx = tid; idx < D * N; idx += kWT) {
+          const int j = idx / N, col = idx % N;
+          const int t = col >= Dr, b = col - (t ? Dr : 0);
+          w.ta[(size_t)(j * 2 + t) * S + b] =
+              j <= col ? cscale(cconj(w.uq[(size_t)col * S + j]), scale) : cd{0.0, 0.0};
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     flags |= wide_jacobi(sh, w.mat, ld, M, N);
     const double tiny2 = sh.tiny2;
     for (int c = tid; c < N; c += kWT) {
@@ -478,7 +521,7 @@ template <typename T, int PROG>
 __global__ __launch_bounds__(kWT) void k_layer_wide(T* state, cd* ws, int n, int chi, int S,
                                                     int layer, const double* theta,
                                                     const double* phi, const double* pixels,
-                                                    double* trunc_err, int* status) {
+                                                    double* trunc_err, int* status, int exact_qr) {
   __shared__ WideShared sh;
   const int b = blockIdx.x;
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
@@ -491,12 +534,12 @@ __global__ __launch_bounds__(kWT) void k_layer_wide(T* state, cd* ws, int n, int
   if (PROG == 1) {
     auto dmid = [&](int k) { return bond_dim(n, chi, (k & 1) ? layer : layer + 1, k); };
     flags |= wide_canon(sh, w, st, S, n, dold, kWGateHRy, theta, phi, pix, false);
-    flags |= wide_cnot(sh, w, st, S, n, dold, dmid, 0, te);
+    flags |= wide_cnot(sh, w, st, S, n, dold, dmid, 0, te, exact_qr);
     flags |= wide_canon(sh, w, st, S, n, dmid, kWGateNone, theta, phi, pix, true);
-    flags |= wide_cnot(sh, w, st, S, n, dmid, dnew, 1, te);
+    flags |= wide_cnot(sh, w, st, S, n, dmid, dnew, 1, te, exact_qr);
   } else {
     flags |= wide_canon(sh, w, st, S, n, dold, kWGateRyRz, theta, phi, pix, false);
-    flags |= wide_cnot(sh, w, st, S, n, dold, dnew, -1, te);
+    flags |= wide_cnot(sh, w, st, S, n, dold, dnew, -1, te, exact_qr);
   }
   if (threadIdx.x == 0 && flags) status[b] |= flags;
 }
@@ -770,10 +813,10 @@ hipError_t launch_layer_wide(T* state, double* ws, int n, int chi, int S, int la
   if (S <= kMaxBond || S > 128) return hipErrorInvalidValue;
   if (program == 1)
     hipLaunchKernelGGL((k_layer_wide<T, 1>), dim3(batch), dim3(kWT), 0, stream, state, (cd*)ws, n,
-                       chi, S, layer, theta, phi, pixels, trunc_err, status);
+                       chi, S, layer, theta, phi, pixels, trunc_err, status, exact_qr());
   else
     hipLaunchKernelGGL((k_layer_wide<T, 0>), dim3(batch), dim3(kWT), 0, stream, state, (cd*)ws, n,
-                       chi, S, layer, theta, phi, pixels, trunc_err, status);
+                       chi, S, layer, theta, phi, pixels, trunc_err, status, exact_qr());
   return hipGetLastError();
 }
 
