@@ -545,6 +545,48 @@ __global__ __launch_bounds__(kWT) void k_layer_wide(T* state, cd* ws, int n, int
 }
 
 // ------------------------------------------------------------------------ measurement
+// C = sum_k A(i, k) B(k, j) over an Mr x Nc output, K terms, in FP64: each lane computes TI x TJ
+// output tiles (consecutive lanes take consecutive column tiles), so each k step loads TI + TJ
+// operands for TI*TJ complex multiply-adds.  `a`, `b` return operands (conjugation and storage
+// type inside), `out(i, j, v)` stores or accumulates.
+template <int TI, int TJ, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void tile_cgemm_t(int Mr, int Nc, int K, FA a, FB b, FC out) {
+  const int ti = (Mr + TI - 1) / TI, tj = (Nc + TJ - 1) / TJ;
+  for (int tile = threadIdx.x; tile < ti * tj; tile += kWT) {
+    const int i0 = (tile / tj) * TI, j0 = (tile % tj) * TJ;
+    cd acc[TI][TJ];
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TJ; ++jj) acc[ii][jj] = cd{0.0, 0.0};
+    for (int k = 0; k < K; ++k) {
+      cd av[TI], bv[TJ];
+#pragma unroll
+      for (int ii = 0; ii < TI; ++ii) av[ii] = (i0 + ii < Mr) ? a(i0 + ii, k) : cd{0.0, 0.0};
+#pragma unroll
+      for (int jj = 0; jj < TJ; ++jj) bv[jj] = (j0 + jj < Nc) ? b(k, j0 + jj) : cd{0.0, 0.0};
+#pragma unroll
+      for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < TJ; ++jj) cfma(acc[ii][jj], av[ii], bv[jj]);
+    }
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TJ; ++jj)
+        if (i0 + ii < Mr && j0 + jj < Nc) out(i0 + ii, j0 + jj, acc[ii][jj]);
+  }
+}
+
+// 4 x 4 tiles when there are enough of them for every lane, 2 x 2 otherwise.
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void tile_cgemm(int Mr, int Nc, int K, FA a, FB b, FC out) {
+  if (Mr * Nc >= 16 * kWT)
+    tile_cgemm_t<4, 4>(Mr, Nc, K, a, b, out);
+  else
+    tile_cgemm_t<2, 2>(Mr, Nc, K, a, b, out);
+}
+
 // Left (side 0) or right (side 1) environments of one image, stored as T in env
 // ([2][n+1][S][S], ket index first), computed in FP64 with E and Tm in the workspace.
 template <typename T>
@@ -572,23 +614,18 @@ __global__ __launch_bounds__(kWT) void k_env_wide(const T* state, T* env, cd* ws
       const int Dl = dim(k - 1), Dr = dim(k);
       const T* A = st + (size_t)k * SLOT;
       // Tm[s][a][b'] = sum_a' E[a][a'] conj(A[a'][s][b'])
-      for (int idx = tid; idx < 2 * Dl * Dr; idx += kWT) {
-        const int s = idx / (Dl * Dr), a = (idx / Dr) % Dl, bp = idx % Dr;
-        cd acc{0.0, 0.0};
-        for (int ap = 0; ap < Dl; ++ap)
-          cfma(acc, E[(size_t)a * S + ap], cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + bp)));
-        Tm[(size_t)(s * S + a) * S + bp] = acc;
-      }
+      for (int s = 0; s < 2; ++s)
+        tile_cgemm(Dl, Dr, Dl, [&](int a, int ap) { return E[(size_t)a * S + ap]; },
+                   [&](int ap, int bp) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + bp)); },
+                   [&](int a, int bp, cd v) { Tm[(size_t)(s * S + a) * S + bp] = v; });
       __syncthreads();
-      // L_{k+1}[b][b'] = sum_s sum_a A[a][s][b] Tm[s][a][b']
-      for (int idx = tid; idx < Dr * Dr; idx += kWT) {
-        const int bb = idx / Dr, bp = idx % Dr;
-        cd acc{0.0, 0.0};
-        for (int s = 0; s < 2; ++s)
-          for (int a = 0; a < Dl; ++a)
-            cfma(acc, load_c<T, double>(A, (size_t)(a * 2 + s) * S + bb), Tm[(size_t)(s * S + a) * S + bp]);
-        E[(size_t)bb * S + bp] = acc;
-      }
+      // L_{k+1}[b][b'] = sum_s sum_a A[a][s][b] Tm[s][a][b']  (k runs over (s, a))
+      tile_cgemm(Dr, Dr, 2 * Dl,
+                 [&](int bb, int k) { const int s = k >= Dl, a = k - (s ? Dl : 0);
+                                      return load_c<T, double>(A, (size_t)(a * 2 + s) * S + bb); },
+                 [&](int k, int bp) { const int s = k >= Dl, a = k - (s ? Dl : 0);
+                                      return Tm[(size_t)(s * S + a) * S + bp]; },
+                 [&](int bb, int bp, cd v) { E[(size_t)bb * S + bp] = v; });
       __syncthreads();
       store_env(k + 1, Dr);
     }
@@ -598,23 +635,18 @@ __global__ __launch_bounds__(kWT) void k_env_wide(const T* state, T* env, cd* ws
       const int Dl = dim(k - 1), Dr = dim(k);
       const T* A = st + (size_t)k * SLOT;
       // Tm[s][c][a'] = sum_c' E[c][c'] conj(A[a'][s][c'])
-      for (int idx = tid; idx < 2 * Dr * Dl; idx += kWT) {
-        const int s = idx / (Dr * Dl), c = (idx / Dl) % Dr, ap = idx % Dl;
-        cd acc{0.0, 0.0};
-        for (int cp = 0; cp < Dr; ++cp)
-          cfma(acc, E[(size_t)c * S + cp], cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + cp)));
-        Tm[(size_t)(s * S + c) * S + ap] = acc;
-      }
+      for (int s = 0; s < 2; ++s)
+        tile_cgemm(Dr, Dl, Dr, [&](int c, int cp) { return E[(size_t)c * S + cp]; },
+                   [&](int cp, int ap) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + cp)); },
+                   [&](int c, int ap, cd v) { Tm[(size_t)(s * S + c) * S + ap] = v; });
       __syncthreads();
-      // R_k[a][a'] = sum_s sum_c A[a][s][c] Tm[s][c][a']
-      for (int idx = tid; idx < Dl * Dl; idx += kWT) {
-        const int a = idx / Dl, ap = idx % Dl;
-        cd acc{0.0, 0.0};
-        for (int s = 0; s < 2; ++s)
-          for (int c = 0; c < Dr; ++c)
-            cfma(acc, load_c<T, double>(A, (size_t)(a * 2 + s) * S + c), Tm[(size_t)(s * S + c) * S + ap]);
-        E[(size_t)a * S + ap] = acc;
-      }
+      // R_k[a][a'] = sum_s sum_c A[a][s][c] Tm[s][c][a']  (k runs over (s, c))
+      tile_cgemm(Dl, Dl, 2 * Dr,
+                 [&](int a, int k) { const int s = k >= Dr, c = k - (s ? Dr : 0);
+                                     return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
+                 [&](int k, int ap) { const int s = k >= Dr, c = k - (s ? Dr : 0);
+                                      return Tm[(size_t)(s * S + c) * S + ap]; },
+                 [&](int a, int ap, cd v) { E[(size_t)a * S + ap] = v; });
       __syncthreads();
       store_env(k, Dl);
     }
@@ -691,21 +723,16 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       const int Dl = dim(i - 1), Dc = dim(i);
       const T* A = st + (size_t)i * SLOT;
       const T* Ev = evl + (size_t)i * s2 * 2;
-      for (int idx = tid; idx < 2 * Dl * Dc; idx += kWT) {
-        const int sp = idx / (Dl * Dc), a = (idx / Dc) % Dl, cp = idx % Dc;
-        cd acc{0.0, 0.0};
-        for (int ap = 0; ap < Dl; ++ap)
-          cfma(acc, load_c<T, double>(Ev, (size_t)a * S + ap), cconj(load_c<T, double>(A, (size_t)(ap * 2 + sp) * S + cp)));
-        Tm[(size_t)(sp * S + a) * S + cp] = acc;
-      }
+      for (int sp = 0; sp < 2; ++sp)
+        tile_cgemm(Dl, Dc, Dl, [&](int a, int ap) { return load_c<T, double>(Ev, (size_t)a * S + ap); },
+                   [&](int ap, int cp) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + sp) * S + cp)); },
+                   [&](int a, int cp, cd v) { Tm[(size_t)(sp * S + a) * S + cp] = v; });
       __syncthreads();
-      for (int idx = tid; idx < 3 * Dc * Dc; idx += kWT) {
-        const int blk = idx / (Dc * Dc), c = (idx / Dc) % Dc, cp = idx % Dc;
+      for (int blk = 0; blk < 3; ++blk) {
         const int s = blk == 2 ? 1 : 0, sp = blk == 0 ? 0 : 1;
-        cd acc{0.0, 0.0};
-        for (int a = 0; a < Dl; ++a)
-          cfma(acc, load_c<T, double>(A, (size_t)(a * 2 + s) * S + c), Tm[(size_t)(sp * S + a) * S + cp]);
-        F[(size_t)(blk * S + c) * S + cp] = acc;
+        tile_cgemm(Dc, Dc, Dl, [&](int c, int a) { return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
+                   [&](int a, int cp) { return Tm[(size_t)(sp * S + a) * S + cp]; },
+                   [&](int c, int cp, cd v) { F[(size_t)(blk * S + c) * S + cp] = v; });
       }
       __syncthreads();
     }
@@ -715,44 +742,36 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       for (; cur < j; ++cur) {
         const int Dc = dim(cur - 1), Dn = dim(cur);
         const T* A = st + (size_t)cur * SLOT;
-        for (int idx = tid; idx < 6 * Dc * Dn; idx += kWT) {
-          const int bu = idx / (Dc * Dn), c = (idx / Dn) % Dc, ep = idx % Dn;
+        for (int bu = 0; bu < 6; ++bu) {
           const int blk = bu >> 1, u = bu & 1;
-          cd acc{0.0, 0.0};
-          for (int cp = 0; cp < Dc; ++cp)
-            cfma(acc, F[(size_t)(blk * S + c) * S + cp], cconj(load_c<T, double>(A, (size_t)(cp * 2 + u) * S + ep)));
-          Tm[(size_t)(bu * S + c) * S + ep] = acc;
+          tile_cgemm(Dc, Dn, Dc, [&](int c, int cp) { return F[(size_t)(blk * S + c) * S + cp]; },
+                     [&](int cp, int ep) { return cconj(load_c<T, double>(A, (size_t)(cp * 2 + u) * S + ep)); },
+                     [&](int c, int ep, cd v) { Tm[(size_t)(bu * S + c) * S + ep] = v; });
         }
         __syncthreads();
-        for (int idx = tid; idx < 3 * Dn * Dn; idx += kWT) {
-          const int blk = idx / (Dn * Dn), e = (idx / Dn) % Dn, ep = idx % Dn;
-          cd acc{0.0, 0.0};
-          for (int u = 0; u < 2; ++u)
-            for (int c = 0; c < Dc; ++c)
-              cfma(acc, load_c<T, double>(A, (size_t)(c * 2 + u) * S + e), Tm[(size_t)((blk * 2 + u) * S + c) * S + ep]);
-          F[(size_t)(blk * S + e) * S + ep] = acc;
-        }
+        for (int blk = 0; blk < 3; ++blk)  // k runs over (u, c)
+          tile_cgemm(Dn, Dn, 2 * Dc,
+                     [&](int e, int k) { const int u = k >= Dc, c = k - (u ? Dc : 0);
+                                         return load_c<T, double>(A, (size_t)(c * 2 + u) * S + e); },
+                     [&](int k, int ep) { const int u = k >= Dc, c = k - (u ? Dc : 0);
+                                          return Tm[(size_t)((blk * 2 + u) * S + c) * S + ep]; },
+                     [&](int e, int ep, cd v) { F[(size_t)(blk * S + e) * S + ep] = v; });
         __syncthreads();
       }
       // close at j: G^{tt'} = A^t R_{j+1} A^{t'H}; rho = sum F^{ss'} (.) G^{tt'}
       const int Dd = dim(j - 1), Dj = dim(j);
       const T* A = st + (size_t)j * SLOT;
       const T* Ev = evr + (size_t)(j + 1) * s2 * 2;
-      for (int idx = tid; idx < 2 * Dj * Dd; idx += kWT) {
-        const int tp = idx / (Dj * Dd), bb = (idx / Dd) % Dj, dp = idx % Dd;
-        cd acc{0.0, 0.0};
-        for (int bp = 0; bp < Dj; ++bp)
-          cfma(acc, load_c<T, double>(Ev, (size_t)bb * S + bp), cconj(load_c<T, double>(A, (size_t)(dp * 2 + tp) * S + bp)));
-        Tm[(size_t)(tp * S + bb) * S + dp] = acc;
-      }
+      for (int tp = 0; tp < 2; ++tp)
+        tile_cgemm(Dj, Dd, Dj, [&](int bb, int bp) { return load_c<T, double>(Ev, (size_t)bb * S + bp); },
+                   [&](int bp, int dp) { return cconj(load_c<T, double>(A, (size_t)(dp * 2 + tp) * S + bp)); },
+                   [&](int bb, int dp, cd v) { Tm[(size_t)(tp * S + bb) * S + dp] = v; });
       __syncthreads();
-      for (int idx = tid; idx < 3 * Dd * Dd; idx += kWT) {
-        const int blk = idx / (Dd * Dd), d = (idx / Dd) % Dd, dp = idx % Dd;
+      for (int blk = 0; blk < 3; ++blk) {
         const int t = blk == 2 ? 1 : 0, tp = blk == 0 ? 0 : 1;
-        cd acc{0.0, 0.0};
-        for (int bb = 0; bb < Dj; ++bb)
-          cfma(acc, load_c<T, double>(A, (size_t)(d * 2 + t) * S + bb), Tm[(size_t)(tp * S + bb) * S + dp]);
-        G[(size_t)(blk * S + d) * S + dp] = acc;
+        tile_cgemm(Dd, Dd, Dj, [&](int d, int bb) { return load_c<T, double>(A, (size_t)(d * 2 + t) * S + bb); },
+                   [&](int bb, int dp) { return Tm[(size_t)(tp * S + bb) * S + dp]; },
+                   [&](int d, int dp, cd v) { G[(size_t)(blk * S + d) * S + dp] = v; });
       }
       __syncthreads();
       // rho[(s,t),(s',t')], entry e = ((s*2+t)*2+s')*2+t'
