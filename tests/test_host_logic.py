@@ -59,3 +59,22 @@ def test_diagonal_pairs(p):
     for i, j in pr:  # grid neighbours (8-neighbourhood)
         ri, ci, rj, cj = i // p, i % p, j // p, j % p
         assert max(abs(ri - rj), abs(ci - cj)) == 1
+
+
+def test_layers_that_keep_every_singular_value():
+    """The exact-split policy's layer test: with chi >= 2^L every layer keeps min(rows, cols)
+    singular values at every bond (so the closed-form dimensions are full rank), and a layer
+    that reaches the chi cap in the middle of the chain does not."""
+    from paper_2607_10280_amd import workload as w
+    for n, chi, L in [(49, 16, 4), (16, 4, 2), (144, 16, 2), (256, 16, 2), (49, 128, 7)]:
+        assert all(w.layer_keeps_all(n, chi, l) for l in range(L)), (n, chi, L)
+    assert [w.layer_keeps_all(49, 8, l) for l in range(4)] == [True, True, True, False]
+    assert [w.layer_keeps_all(49, 2, l) for l in range(3)] == [True, False, False]
+    # a truncating layer's middle bond: D = chi < min(rows, cols)
+    n, chi, l, k = 49, 8, 3, 20
+    D = w.bond(n, chi, l + 1, k)
+    assert D == 8 and min(2 * w.bond(n, chi, l + 1, k - 1), 2 * w.bond(n, chi, l, k + 1)) == 16
+    # the QR path is priced below the SVD path and reads/writes each tensor once
+    f_qr, f_svd = w.layer_flops(49, 16, 3), w.layer_flops(49, 16, 3, exact_qr=False)
+    assert f_qr["svd_fp64"] == 0 and 0 < f_qr["total_fp64"] < f_svd["total_fp64"]
+    assert w.layer_bytes(49, 16, 3, 4) == w.state_bytes(49, 16, 3, 4) + w.state_bytes(49, 16, 4, 4)
