@@ -252,21 +252,27 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   return kImgNoConvergence;  // unreachable for shapes within the slot
 }
 
-// Householder QR of A = t^H (M rows, N <= M columns, column-major in `mat`, rows [0, M) read)
-// in FP64, used by the canonical sweep: t = L Q with L = R^H lower-triangular (N x N) and
-// Q = (first N columns of H_0 ... H_{N-1})^H with orthonormal rows.  A team of TM lanes owns
-// column c; lane lt holds rows lt + t*TM (R per lane) in registers.  Step j reflects rows [j, M)
-// of column j onto beta_j e_j with H_j = I - coef_j v_j v_j^H (beta_j = -e^{i arg a_jj} |a_j|,
-// the sign that avoids cancellation), publishes v_j in mat column j and coef_j in sig2[j], and
-// every later column takes the reflection.  A column whose remaining part has |.|^2 <= 1e-30
-// |A|_F^2 is left as it is (H_j = I).  Q is then formed by applying H_{N-1}, ..., H_0 to the
-// first N unit vectors.
-// Out: uq[j*SP + a] = L[j][a] = conj(R[a][j]).  LADDER = false (canonical sweep): rows of Q
-// conjugated into the site slot as [a][s][b] (row index r = s*Dr + b).  LADDER = true (a
-// two-site matrix Theta = Q R split without truncation): Q itself into the slot as
-// [(a,s)][j], row index r = a*2 + s, column j.
-template <int S, typename T, int NC, int R, bool LADDER>
-__device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
+// Householder QR in FP64 of the columns in `mat` (column-major, leading dimension LD, rows
+// [0, M) read), in independent blocks of ncb consecutive columns (N = total columns, a multiple
+// of ncb, ncb <= M): each block B = Q R with Q (M x ncb) orthonormal columns and R upper
+// triangular.  A team of TM lanes owns column c; lane lt holds rows lt + t*TM (R per lane) in
+// registers.  Step j reflects rows [j, M) of each block's column j onto beta_j e_j with
+// H_j = I - coef_j v_j v_j^H (beta_j = -e^{i arg a_jj} |a_j|, the sign that avoids
+// cancellation), publishes v_j in its column of mat and coef_j in sig2, and the later columns of
+// the same block take the reflection.  A column whose remaining part has |.|^2 <= 1e-30
+// |A|_F^2 is left as it is (H_j = I).  Q is formed by applying H_{ncb-1}, ..., H_0 to the
+// first ncb unit vectors.  Out: uq[c*SP + a] = conj(R[a][c]) (block-local row a, global column
+// c), and Q into the site slot:
+//  kHhCanon  (one block; canonical sweep, A = t^H, t = L Q^H with L = R^H): rows of Q^H as
+//            [a][s][b], row index r = s*Dr + b;
+//  kHhLadder (one block; Theta = Q R or the centre alone split as Q R): Q as [(a,s)][c], row
+//            index r = a*2 + s;
+//  kHhBlock2 (two blocks u = 0, 1 holding the s = u rows of the centre): A[(a,s)][c] =
+//            Q_u[a][c - u*ncb] if s = u, else 0.
+enum : int { kHhCanon = 0, kHhLadder = 1, kHhBlock2 = 2 };
+
+template <int S, typename T, int NC, int R, int MODE>
+__device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
   constexpr int TM = (kLayerThreads / NC) < 16 ? kLayerThreads / NC : 16;
@@ -274,6 +280,7 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
   const int tid = threadIdx.x;
   const int c = tid / TM, lt = tid % TM;
   const bool own = c < N;
+  const int blk = own ? c / ncb : 0, lc = c - blk * ncb, base = blk * ncb;
   cd x[R];
   double f = 0.0;
 #pragma unroll
@@ -283,8 +290,8 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
     f = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, f));
   }
   const double tiny2 = 1e-30 * block_sum(f, sh.red);
-  for (int j = 0; j < N; ++j) {
-    // |rows >= j|^2 and the diagonal entry of this team's column (used by team j only).
+  for (int j = 0; j < ncb; ++j) {
+    // |rows >= j|^2 and the diagonal entry of this team's column (used by the pivot teams).
     double a2 = 0.0, dr = 0.0, di = 0.0;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
@@ -295,7 +302,7 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
     a2 = team_sum<TM>(a2);
     dr = team_sum<TM>(dr);
     di = team_sum<TM>(di);
-    if (c == j) {
+    if (own && lc == j) {
       cd beta{dr, di}, v0{dr, di};
       double coef = 0.0;
       if (a2 > tiny2) {
@@ -314,20 +321,21 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
         cd v = x[t];
         if (rr < j) v = cd{0.0, 0.0};
         if (rr == j) v = v0;
-        if (rr < LD) sh.mat[j * LD + rr] = v;
-        // Column j of R: entries above the diagonal, beta on it; L = R^H.
-        if (rr < N) sh.uq[j * SP + rr] = rr < j ? cconj(x[t]) : (rr == j ? cconj(beta) : cd{0.0, 0.0});
+        if (rr < LD) sh.mat[c * LD + rr] = v;
+        // Column j of the block's R: entries above the diagonal, beta on it.
+        if (rr < ncb) sh.uq[c * SP + rr] = rr < j ? cconj(x[t]) : (rr == j ? cconj(beta) : cd{0.0, 0.0});
       }
-      if (lt == 0) sh.sig2[j] = coef;
+      if (lt == 0) sh.sig2[c] = coef;
     }
     __syncthreads();
-    if (c > j && own) {
-      const double coef = sh.sig2[j];
+    if (own && lc > j) {
+      const int pc = base + j;
+      const double coef = sh.sig2[pc];
       cd v[R];
       double gr = 0.0, gi = 0.0;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        v[t] = sh.mat[j * LD + lt + t * TM];
+        v[t] = sh.mat[pc * LD + lt + t * TM];
         gr = fma(v[t].re, x[t].re, fma(v[t].im, x[t].im, gr));     // v^H x
         gi = fma(v[t].re, x[t].im, fma(-v[t].im, x[t].re, gi));
       }
@@ -340,16 +348,17 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
       }
     }
   }
-  // Q columns: e_c through H_{N-1}, ..., H_0 (column c only meets H_j for j <= c).
+  // Q columns: e_lc through H_{ncb-1}, ..., H_0 of the block (column lc only meets H_j, j <= lc).
 #pragma unroll
-  for (int t = 0; t < R; ++t) x[t] = cd{(lt + t * TM == c) ? 1.0 : 0.0, 0.0};
-  for (int j = N - 1; j >= 0; --j) {
-    const double coef = sh.sig2[j];
+  for (int t = 0; t < R; ++t) x[t] = cd{(lt + t * TM == lc) ? 1.0 : 0.0, 0.0};
+  for (int j = ncb - 1; j >= 0; --j) {
+    const int pc = base + j;
+    const double coef = own ? sh.sig2[pc] : 0.0;
     cd v[R];
     double gr = 0.0, gi = 0.0;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
-      v[t] = sh.mat[j * LD + lt + t * TM];
+      v[t] = sh.mat[pc * LD + lt + t * TM];
       gr = fma(v[t].re, x[t].re, fma(v[t].im, x[t].im, gr));
       gi = fma(v[t].re, x[t].im, fma(-v[t].im, x[t].re, gi));
     }
@@ -366,10 +375,13 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int Dr, T* s
     for (int t = 0; t < R; ++t) {
       const int rr = lt + t * TM;
       if (rr < M) {
-        if constexpr (LADDER) {
+        if constexpr (MODE == kHhLadder) {
           store_c<T, double>(slot, (size_t)rr * S + c, x[t]);  // Q[rr][c]
+        } else if constexpr (MODE == kHhBlock2) {
+          store_c<T, double>(slot, (size_t)(rr * 2 + blk) * S + c, x[t]);
+          store_c<T, double>(slot, (size_t)(rr * 2 + 1 - blk) * S + c, cd{0.0, 0.0});
         } else {
-          // row c of Q = conj(column c of the product)
+          // row c of Q^H = conj(column c of Q)
           const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
           store_c<T, double>(slot, (size_t)(c * 2 + s_) * S + b, cconj(x[t]));
         }
@@ -385,19 +397,19 @@ __host__ __device__ inline int lq_rows_per_lane(int M, int N) {
   return pow2ceil((M + tm - 1) / tm);
 }
 
-template <int S, typename T, bool LADDER>
-__device__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int Dr, T* slot) {
+template <int S, typename T, int MODE>
+__device__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
   const int nc = pow2ceil(N < 1 ? 1 : N), r = lq_rows_per_lane(M, N);
 #define ANOMPS_LQ(NCV, RV)                                                                  \
   if (nc == NCV && r == RV) {                                                              \
-    if constexpr (NCV <= S && RV * ((kLayerThreads / NCV) < 16 ? kLayerThreads / NCV : 16) <= \
-                                  LayerShared<S, T>::LD) {                                 \
-      householder_lq<S, T, NCV, RV, LADDER>(sh, M, N, Dr, slot);                           \
+    if constexpr (NCV <= 2 * S && RV * ((kLayerThreads / NCV) < 16 ? kLayerThreads / NCV : 16) <= \
+                                      LayerShared<S, T>::LD) {                             \
+      householder_lq<S, T, NCV, RV, MODE>(sh, M, N, ncb, Dr, slot);                        \
       return 0;                                                                            \
     }                                                                                      \
   }
 #define ANOMPS_LQN(NCV) ANOMPS_LQ(NCV, 1) ANOMPS_LQ(NCV, 2) ANOMPS_LQ(NCV, 4) ANOMPS_LQ(NCV, 8)
-  ANOMPS_LQN(1) ANOMPS_LQN(2) ANOMPS_LQN(4) ANOMPS_LQN(8) ANOMPS_LQN(16)
+  ANOMPS_LQN(1) ANOMPS_LQN(2) ANOMPS_LQN(4) ANOMPS_LQN(8) ANOMPS_LQN(16) ANOMPS_LQN(32)
 #undef ANOMPS_LQN
 #undef ANOMPS_LQ
   return kImgNoConvergence;  // unreachable for shapes within the slot
@@ -533,7 +545,7 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
     }
     __syncthreads();
     // t = L Q: Q (right-canonical rows) goes to site k, L to uq.
-    flags |= lq_columns<S, T, false>(sh, M, N, Dr, st + (size_t)k * SLOT);
+    flags |= lq_columns<S, T, kHhCanon>(sh, M, N, N, Dr, st + (size_t)k * SLOT);
     pf.commit(sh.tb);
     __syncthreads();
     const FastDiv fdl(Dl);
@@ -570,6 +582,22 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
     pf.commit(sh.tb);
     __syncthreads();
     if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
+    if (exact_qr && ((cx && D == 2 * Dc && Dl >= Dc) || (!cx && D == Dc && 2 * Dl >= Dc))) {
+      // The bond keeps every singular value of a factorisation with inner dimension D: split
+      // it without the two-site matrix.  The centre is in canonical position, so the kept
+      // weight is |centre|_F^2 (the CNOT is unitary, A[k+1] right-orthonormal).
+      const double f = centre_norm2<S, T>(sh, Dl, Dc);
+      if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
+      const double scale = f > 0.0 ? rsqrt_full(f) : 0.0;
+      if (cx) {
+        const Gate2 none{};
+        flags |= block_split<S, T>(sh, st + (size_t)k * SLOT, Dl, Dc, Dr, none, false, scale);
+        if (tid == 0 && trunc_err) trunc_err[k] = 0.0;
+      } else {
+        flags |= plain_split<S, T>(sh, st + (size_t)k * SLOT, Dl, Dc, Dr, scale);
+      }
+      continue;
+    }
     const int M = 2 * Dl, N = 2 * Dr;
     const int MP = jacobi_shape(M, N).MP;
     // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR (cx s), b]   (CNOT control k).
@@ -698,7 +726,7 @@ __device__ __forceinline__ int exact_split(LayerShared<S, T>& sh, T* slot, int M
       sh.ta[(j * 2 + t) * SP + b] = cscale(sh.mat[col * LD + j], scale);
     }
   } else {
-    flags |= lq_columns<S, T, true>(sh, M, N, Dr, slot);
+    flags |= lq_columns<S, T, kHhLadder>(sh, M, N, N, Dr, slot);
     for (int idx = tid; idx < D * N; idx += kLayerThreads) {
       const int j = fn.q(idx), col = fn.r(idx);
       const int t = col >= Dr, b = col - (t ? Dr : 0);
@@ -706,6 +734,95 @@ __device__ __forceinline__ int exact_split(LayerShared<S, T>& sh, T* slot, int M
     }
   }
   return flags;
+}
+
+// Split of a CNOT bond through its rank-2Dc factorisation, exact when the bond keeps D = 2 Dc
+// values and Dl >= Dc: Theta'[(a,s),(t,b)] = sum_c ta[a,s,c] (U B)[c, t XOR s, b] factors as
+// blockdiag(ta_0, ta_1) times [(U B)[c, t XOR u, b]] with ta_u = ta[:, u, :] (Dl x Dc), so
+// ta_u = Q_u R_u (two independent Householder blocks) gives A[k][(a,s)][(u,c')] = Q_s[a][c']
+// (zero for s != u) and centre[(u,c')][(t,b)] = sum_c R_u[c'][c] (U B)[c][t XOR u][b] -- no
+// two-site matrix and half the Householder steps.  U = the one-qubit gate of site k+1 when
+// `gate` (else the identity); the centre is multiplied by `scale`.
+template <int S, typename T>
+__device__ __forceinline__ int block_split(LayerShared<S, T>& sh, T* slot, int Dl, int Dc, int Dr,
+                                           const Gate2& g, bool gate, double scale) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x;
+  {
+    const FastDiv fdl(Dl);
+    for (int idx = tid; idx < 2 * Dc * Dl; idx += kLayerThreads) {
+      const int col = fdl.q(idx), a = fdl.r(idx);
+      const int u = col >= Dc, c = col - (u ? Dc : 0);
+      sh.mat[col * LD + a] = sh.ta[(a * 2 + u) * SP + c];
+    }
+  }
+  __syncthreads();
+  int flags = lq_columns<S, T, kHhBlock2>(sh, Dl, 2 * Dc, Dc, 0, slot);
+  const FastDiv f2r(2 * Dr);
+  for (int idx = tid; idx < 2 * Dc * 2 * Dr; idx += kLayerThreads) {
+    const int j = f2r.q(idx), o = f2r.r(idx);
+    const int t = o >= Dr, b = o - (t ? Dr : 0);
+    const int u = j >= Dc, cp = j - (u ? Dc : 0), tt = t ^ u;
+    cd acc{0.0, 0.0};
+    for (int c = cp; c < Dc; ++c) {
+      cd bv;
+      if (gate) {
+        const cd b0 = to_cd(sh.tb[(c * 2) * SP + b]), b1 = to_cd(sh.tb[(c * 2 + 1) * SP + b]);
+        bv = tt ? cmul(g.u10, b0) : cmul(g.u00, b0);
+        cfma(bv, tt ? g.u11 : g.u01, b1);
+      } else {
+        bv = to_cd(sh.tb[(c * 2 + tt) * SP + b]);
+      }
+      cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), bv);
+    }
+    sh.ta[(j * 2 + t) * SP + b] = cscale(acc, scale);
+  }
+  __syncthreads();
+  return flags;
+}
+
+// Centre move without a gate, exact when the bond keeps D = Dc values and 2 Dl >= Dc: the
+// centre (2Dl x Dc) = Q R, A[k] <- Q, centre <- R A[k+1] (times `scale`).
+template <int S, typename T>
+__device__ __forceinline__ int plain_split(LayerShared<S, T>& sh, T* slot, int Dl, int Dc, int Dr,
+                                           double scale) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x;
+  const int M = 2 * Dl;
+  {
+    const FastDiv fm(M);
+    for (int idx = tid; idx < Dc * M; idx += kLayerThreads) {
+      const int c = fm.q(idx), row = fm.r(idx);
+      sh.mat[c * LD + row] = sh.ta[row * SP + c];
+    }
+  }
+  __syncthreads();
+  int flags = lq_columns<S, T, kHhLadder>(sh, M, Dc, Dc, 0, slot);
+  const FastDiv f2r(2 * Dr);
+  for (int idx = tid; idx < Dc * 2 * Dr; idx += kLayerThreads) {
+    const int j = f2r.q(idx), o = f2r.r(idx);
+    const int t = o >= Dr, b = o - (t ? Dr : 0);
+    cd acc{0.0, 0.0};
+    for (int c = j; c < Dc; ++c) cfma(acc, cconj(sh.uq[c * SP + j]), to_cd(sh.tb[(c * 2 + t) * SP + b]));
+    sh.ta[(j * 2 + t) * SP + b] = cscale(acc, scale);
+  }
+  __syncthreads();
+  return flags;
+}
+
+// |ta|_F^2 of a (Dl x 2 x Dc) centre.
+template <int S, typename T>
+__device__ __forceinline__ double centre_norm2(LayerShared<S, T>& sh, int Dl, int Dc) {
+  constexpr int SP = LayerShared<S, T>::SP;
+  double f = 0.0;
+  const FastDiv fdc(Dc);
+  for (int idx = threadIdx.x; idx < 2 * Dl * Dc; idx += kLayerThreads) {
+    const cd v = sh.ta[fdc.q(idx) * SP + fdc.r(idx)];
+    f = fma(v.re, v.re, fma(v.im, v.im, f));
+  }
+  return block_sum(f, sh.red);
 }
 
 // True when layer `layer` of the CNOT-ladder circuit keeps every singular value at every bond:
@@ -752,6 +869,12 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
     pf.commit(sh.tb);
     __syncthreads();
     if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
+    if (D == 2 * Dc && Dl >= Dc) {
+      flags |= block_split<S, T>(sh, st + (size_t)k * SLOT, Dl, Dc, Dr,
+                                 site_gate(kGateRyRz, k + 1, theta, phi, nullptr), true, 1.0);
+      if (tid == 0 && trunc_err) trunc_err[k] = 0.0;
+      continue;
+    }
     // gated neighbour in FP64: uq[(c*2 + t)*SP + b]
     {
       const Gate2 g = site_gate(kGateRyRz, k + 1, theta, phi, nullptr);
