@@ -42,8 +42,9 @@ def householder_qr_flops(m: int, n: int) -> float:
 
 def layer_flops(n: int, chi: int, layer: int, exact_qr: bool = True) -> dict:
     """Work of applying layer `layer` (0-based) to one image.  A layer that keeps every singular
-    value (and exact_qr) is one sweep: gate the neighbour, contract Theta', split it by
-    Householder QR (or not at all when D equals its row count).  Otherwise: canonical sweep
+    value (and exact_qr) is one sweep: gate the neighbour, then split each bond exactly -- through
+    two Householder blocks of the centre when D = 2 D_old (no two-site matrix), else contract
+    Theta' and split it by Householder QR (or not at all when D equals its row count).  Otherwise: canonical sweep
     (gate + SVD of each site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left
     neighbour), then the ladder (two-site contraction, SVD, U^H Theta' for the new centre)."""
     d_old = lambda k: bond(n, chi, layer, k)
@@ -54,9 +55,16 @@ def layer_flops(n: int, chi: int, layer: int, exact_qr: bool = True) -> dict:
         for k in range(n - 1):
             dl, dc, dr, d = d_new(k - 1), d_old(k), d_old(k + 1), d_new(k)
             rows, cols = 2 * dl, 2 * dr
-            other += CMAC * (4 * dc * dr + rows * cols * dc)
-            if d != rows:
-                qr += householder_qr_flops(rows, cols)
+            other += CMAC * 4 * dc * dr                      # gate on site k+1
+            if d == 2 * dc and dl >= dc:
+                # two Householder blocks of the centre (Dl x Dc each), then the centre
+                # R (triangular) times the gated neighbour
+                qr += 2 * householder_qr_flops(dl, dc)
+                other += CMAC * d * cols * (dc + 1) / 2
+            else:
+                other += CMAC * rows * cols * dc             # two-site matrix
+                if d != rows:
+                    qr += householder_qr_flops(rows, cols)
         return {"qr_fp64": qr, "svd_fp64": 0.0, "other_fp64": other, "total_fp64": qr + other}
     svd = other = 0.0
     for k in range(n - 1, 0, -1):
