@@ -749,12 +749,30 @@ __device__ __forceinline__ int block_split(LayerShared<S, T>& sh, T* slot, int D
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
   const int tid = threadIdx.x;
+  // 2 Dc = D <= S, so mat's columns [S, 2S) are free during the QR: the neighbour (gated in
+  // FP64 when `gate`) goes there as gb[(c*2 + t)*SP + b].
+  cd* gb = sh.mat + S * LD;
   {
     const FastDiv fdl(Dl);
     for (int idx = tid; idx < 2 * Dc * Dl; idx += kLayerThreads) {
       const int col = fdl.q(idx), a = fdl.r(idx);
       const int u = col >= Dc, c = col - (u ? Dc : 0);
       sh.mat[col * LD + a] = sh.ta[(a * 2 + u) * SP + c];
+    }
+    const FastDiv fdr(Dr);
+    for (int idx = tid; idx < Dc * Dr; idx += kLayerThreads) {
+      const int c = fdr.q(idx), b = fdr.r(idx);
+      const cd b0 = to_cd(sh.tb[(c * 2) * SP + b]), b1 = to_cd(sh.tb[(c * 2 + 1) * SP + b]);
+      if (gate) {
+        cd w0 = cmul(g.u00, b0), w1 = cmul(g.u10, b0);
+        cfma(w0, g.u01, b1);
+        cfma(w1, g.u11, b1);
+        gb[(c * 2) * SP + b] = w0;
+        gb[(c * 2 + 1) * SP + b] = w1;
+      } else {
+        gb[(c * 2) * SP + b] = b0;
+        gb[(c * 2 + 1) * SP + b] = b1;
+      }
     }
   }
   __syncthreads();
@@ -765,17 +783,7 @@ __device__ __forceinline__ int block_split(LayerShared<S, T>& sh, T* slot, int D
     const int t = o >= Dr, b = o - (t ? Dr : 0);
     const int u = j >= Dc, cp = j - (u ? Dc : 0), tt = t ^ u;
     cd acc{0.0, 0.0};
-    for (int c = cp; c < Dc; ++c) {
-      cd bv;
-      if (gate) {
-        const cd b0 = to_cd(sh.tb[(c * 2) * SP + b]), b1 = to_cd(sh.tb[(c * 2 + 1) * SP + b]);
-        bv = tt ? cmul(g.u10, b0) : cmul(g.u00, b0);
-        cfma(bv, tt ? g.u11 : g.u01, b1);
-      } else {
-        bv = to_cd(sh.tb[(c * 2 + tt) * SP + b]);
-      }
-      cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), bv);
-    }
+    for (int c = cp; c < Dc; ++c) cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), gb[(c * 2 + tt) * SP + b]);
     sh.ta[(j * 2 + t) * SP + b] = cscale(acc, scale);
   }
   __syncthreads();
