@@ -34,12 +34,12 @@ PEAK_HBM_GBS = 8000.0
 # the factors a 1 GiB device copy reads), valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
     "layer": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-              "sha1": "482f4cea50558dfb01c5914e1ba7c42af2d1e36e",
-              "bytes": (2 * 22732.1 + 59777.0) * 1024},
+              "sha1": "a78cbff4a2b616629735c1221410f46758e1302a",
+              "bytes": (2 * 22730.7 + 59777.5) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
                 "sha1": "94c4332b93ffdbfe8d62c543474359cbd0cf8ca7",
-                "bytes": (2 * (172139.9 + 188520.0) + (204800.0 + 5264.5)) * 1024},
+                "bytes": (2 * (172218.9 + 188543.7) + (204800.0 + 5276.7)) * 1024},
 }
 
 
