@@ -1,7 +1,7 @@
 // Matrix-core versions of the environment sweeps and pair expectations for 16-wide bonds
-// (§II-C, Eq. (4)-(5)).  Every contraction is a 16x16x16 complex product made of four real
-// products (re*re, -im*im, re*im, im*re).  FP32: each real product is four
-// v_mfma_f32_16x16x4f32 (one per k-chunk).  Split-BF16: each FP32 operand x is written as
+// (§II-C, Eq. (4)-(5)).  Every contraction is a 16x16x16 complex product.  FP32: three real
+// products (Gauss: Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)), each four v_mfma_f32_16x16x4f32 (one per
+// k-chunk).  Split-BF16: four real products (re*re, -im*im, re*im, im*re).  Split-BF16: each FP32 operand x is written as
 // x_hi + x_lo with x_hi = bf16(x) and x_lo = bf16(x - x_hi), and each real product as
 // a_hi b_hi + a_hi b_lo + a_lo b_hi in three v_mfma_f32_16x16x16_bf16 (FP32 accumulation); the
 // dropped a_lo b_lo term and the two roundings leave a relative error of at most ~3 * 2^-18
@@ -83,13 +83,17 @@ __device__ __forceinline__ f4 mfma_split(const Split4& a, const Split4& b, f4 c)
 template <bool SPLIT>
 __device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]) {
   if constexpr (!SPLIT) {
+    // Three real products (Gauss): re = Ar Br - Ai Bi, im = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi,
+    // as three independent chains of four MFMAs.
+    f4 t1 = f4{0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      c.re = mfma(a[kc].re, b[kc].re, c.re);
-      c.re = mfma(-a[kc].im, b[kc].im, c.re);
-      c.im = mfma(a[kc].re, b[kc].im, c.im);
-      c.im = mfma(a[kc].im, b[kc].re, c.im);
+      t1 = mfma(a[kc].re, b[kc].re, t1);
+      t2 = mfma(a[kc].im, b[kc].im, t2);
+      t3 = mfma(a[kc].re + a[kc].im, b[kc].re + b[kc].im, t3);
     }
+    c.re += t1 - t2;
+    c.im += t3 - t1 - t2;
   } else {
     const Split4 ar = split4(a[0].re, a[1].re, a[2].re, a[3].re, false);
     const Split4 ai = split4(a[0].im, a[1].im, a[2].im, a[3].im, false);
