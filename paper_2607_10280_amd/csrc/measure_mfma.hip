@@ -477,8 +477,10 @@ __global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int
               layers, side);
 }
 
+// Three waves per SIMD instead of the two its 246 registers allow: the compiler spills ~100
+// bytes per lane, and the launch is ~4 % faster with the extra wave hiding MFMA and LDS latency.
 template <bool SPLIT>
-__global__ __launch_bounds__(W) void k_pairs16(const float* state, const float* env,
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pairs16(const float* state, const float* env,
                                                 const int* pairs, int m, int n, int chi,
                                                 int layers, int batch, float* out) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
