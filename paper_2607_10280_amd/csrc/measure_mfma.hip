@@ -433,16 +433,29 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
         } else {
           fv = gt ? fb[s + sp] : fa[s + sp];
         }
-        part[2 * e] += fv.re * gv.re - fv.im * gv.im;
-        part[2 * e + 1] += fv.re * gv.im + fv.im * gv.re;
+        // rho is Hermitian (row (s,t) = e >> 2, column (s',t') = e & 3): only the upper
+        // triangle is accumulated, and only the real part on the diagonal.
+        if ((e >> 2) <= (e & 3)) {
+          part[2 * e] += fv.re * gv.re - fv.im * gv.im;
+          if ((e >> 2) < (e & 3)) part[2 * e + 1] += fv.re * gv.im + fv.im * gv.re;
+        }
       }
     }
 #pragma unroll
-    for (int e = 0; e < 32; ++e) part[e] = wave_sum_f(part[e]);
+    for (int e = 0; e < 16; ++e) {
+      if ((e >> 2) <= (e & 3)) part[2 * e] = wave_sum_f(part[2 * e]);
+      if ((e >> 2) < (e & 3)) part[2 * e + 1] = wave_sum_f(part[2 * e + 1]);
+    }
     if (l < 32) {
+      // entry e = l/2; a lower-triangle entry is the conjugate of its transpose e' = col*4 + row
+      const int e = l >> 1, row = e >> 2, col = e & 3;
+      const int src = row <= col ? e : col * 4 + row;
+      const bool im = l & 1;
       float v = 0.f;
 #pragma unroll
-      for (int e = 0; e < 32; ++e) v = (l == e) ? part[e] : v;
+      for (int x = 0; x < 32; ++x) v = (x == 2 * src + (im ? 1 : 0)) ? part[x] : v;
+      if (im && row > col) v = -v;
+      if (im && row == col) v = 0.f;
       rho[l] = v;
     }
     __syncthreads();
