@@ -35,11 +35,11 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "layer": {"source": "paper_2607_10280_amd/csrc/layer.hip",
               "sha1": "a78cbff4a2b616629735c1221410f46758e1302a",
-              "bytes": (2 * 22714.1 + 59777.2) * 1024},
+              "bytes": (2 * 22727.5 + 59776.8) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "003a34240c54a7e66f92222274a214012754bbd9",
-                "bytes": (2 * (173286.5 + 282463.4) + (204800.0 + 296089.1)) * 1024},
+                "sha1": "0473b8e9612fd853869a6e4a849b87bbf81aaaf0",
+                "bytes": (2 * (173292.0 + 274482.7) + (204800.0 + 294760.6)) * 1024},
 }
 
 
