@@ -148,23 +148,31 @@ int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double
                     hipStream_t stream);
 
 /*
- * How mps_apply_layer (and the mixed layer step) split the bonds of a layer in which the bond
- * rule keeps every singular value, i.e. D_k = min(2 D_{k-1}, 2 D_{k+1}^old) at every bond k
- * (always the case when chi >= 2^n_layers, the exact regime of §II-B):
- *  MPS_EXACT_QR (default): one left-to-right sweep; each two-site matrix Theta' is split
- *    exactly, by Householder QR in FP64 (A[k] <- Q, centre <- R) or, when D_k equals its row
- *    count, as A[k] <- identity, centre <- Theta'; the one-qubit gates are applied as each
- *    site is reached, the last centre is scaled to unit norm, and trunc_err is 0.  Nothing can
- *    be discarded in such a layer, so the state is the one the SVD ladder produces (up to
- *    rounding and the gauge of each bond) and the features agree to rounding.
+ * How mps_apply_layer (and the mixed layer step) handle a layer in which the bond rule keeps
+ * every singular value, i.e. D_k = min(2 D_{k-1}, 2 D_{k+1}^old) at every bond k (always the
+ * case when chi >= 2^n_layers, the exact regime of §II-B).  Nothing can be discarded in such a
+ * layer, so every mode below produces the state the SVD ladder produces (up to rounding and
+ * the gauge of each bond), the features agree to rounding, and trunc_err is 0.
+ *  MPS_EXACT_MPO (default): the CNOT ladder is the product operator that maps each bit to the
+ *    parity of the bits up to it (bond dimension 2), so the layer is applied site by site:
+ *    B[k][(p,a), y, (q,b)] = (U_k A[k])[a, y XOR p, b] delta(q, y), U_k = R_Y R_Z of site k.
+ *    Where the rule keeps D_k < 2 D_k^old (the chain ends) the doubled bond is reduced exactly:
+ *    those sites become identity tensors and the product of their B's is carried into the
+ *    first site with a full bond.  No site is orthonormalised (the norm is the input's, the
+ *    layer being unitary); the measurement contracts both environments and needs no gauge.
+ *    Slots wider than 16 take these layers like the truncating ones (next paragraph).
+ *  MPS_EXACT_QR: one left-to-right sweep; each two-site matrix Theta' is split exactly, by
+ *    Householder QR in FP64 (A[k] <- Q, centre <- R) or, when D_k equals its row count, as
+ *    A[k] <- identity, centre <- Theta'; the one-qubit gates are applied as each site is
+ *    reached and the last centre is scaled to unit norm.
  *  MPS_EXACT_SVD: the canonical sweep + Jacobi SVD ladder, as for every other layer.
  * Layers with any truncating bond, the H-R_Y brickwork program and slots wider than 16 keep the
- * canonical sweep; under MPS_EXACT_QR their ladder still splits each bond that keeps all
- * min(rows, cols) singular values exactly (identity or QR, centre renormalised by |Theta'|)
- * and runs the Jacobi SVD only where weight can be discarded.  Process-wide setting, read at
- * each launch.  Returns MPS_ERR_INVALID_ARG for another mode.
+ * canonical sweep; under MPS_EXACT_MPO and MPS_EXACT_QR their ladder still splits each bond
+ * that keeps all min(rows, cols) singular values exactly (identity or QR, centre renormalised
+ * by |Theta'|) and runs the Jacobi SVD only where weight can be discarded.  Process-wide
+ * setting, read at each launch.  Returns MPS_ERR_INVALID_ARG for another mode.
  */
-enum { MPS_EXACT_QR = 0, MPS_EXACT_SVD = 1 };
+enum { MPS_EXACT_QR = 0, MPS_EXACT_SVD = 1, MPS_EXACT_MPO = 2 };
 int mps_set_exact_layers(int32_t mode);
 
 /* Layer programs of mps_apply_layer_program. */

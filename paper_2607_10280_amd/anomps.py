@@ -372,12 +372,13 @@ def pauli_pair_expect_mixed(table, plan: MixedPlan, stream=None) -> None:
     _check(lib().mps_pauli_pair_expect_mixed(_ptr(table), ctypes.byref(plan), _stream(stream)))
 
 
-EXACT_QR, EXACT_SVD = 0, 1
+EXACT_QR, EXACT_SVD, EXACT_MPO = 0, 1, 2
 
 
 def set_exact_layers(mode: int) -> None:
-    """EXACT_QR (default): ladder layers that keep every singular value are split by QR in one
-    sweep; EXACT_SVD: canonical sweep + Jacobi SVD for every layer."""
+    """Ladder layers that keep every singular value: EXACT_MPO (default) applies them site by
+    site as the parity product operator with exact reduction at the chain ends; EXACT_QR splits
+    them by QR in one sweep; EXACT_SVD runs the canonical sweep + Jacobi SVD for every layer."""
     _check(lib().mps_set_exact_layers(mode))
 
 

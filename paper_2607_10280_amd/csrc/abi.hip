@@ -389,8 +389,12 @@ int mps_pauli_pair_expect_mixed(const mps_request* reqs, const mps_mixed_plan* p
 }
 
 int mps_set_exact_layers(int32_t mode) {
-  if (mode != MPS_EXACT_QR && mode != MPS_EXACT_SVD) return fail(MPS_ERR_INVALID_ARG, "mode=%d", mode);
-  set_exact_qr(mode == MPS_EXACT_QR);
+  switch (mode) {
+    case MPS_EXACT_MPO: set_exact_qr(kExactMpo); break;
+    case MPS_EXACT_QR: set_exact_qr(kExactQr); break;
+    case MPS_EXACT_SVD: set_exact_qr(kExactSvd); break;
+    default: return fail(MPS_ERR_INVALID_ARG, "mode=%d", mode);
+  }
   return ok();
 }
 

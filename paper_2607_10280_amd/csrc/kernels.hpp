@@ -18,9 +18,12 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
                         const double* theta, const double* phi, const double* pixels,
                         double* trunc_err, int* status, hipStream_t stream);
 
-// Ladder layers in which every bond keeps all its singular values: split by Householder QR in
-// one sweep (on, the default) or by the canonical sweep + Jacobi SVD ladder (off).
-void set_exact_qr(int on);
+// Bonds and ladder layers that keep all their singular values: kExactMpo (default) applies such
+// a layer as one site-local contraction and splits other such bonds exactly; kExactQr splits
+// every bond of such a layer by Householder QR in one sweep; kExactSvd runs the canonical sweep
+// + Jacobi SVD ladder everywhere.  Kernels test the mode for non-zero to enable the exact splits.
+enum : int { kExactSvd = 0, kExactQr = 1, kExactMpo = 2 };
+void set_exact_qr(int mode);
 int exact_qr();
 
 // Environment sweeps (left and right) and pair expectations.  T = storage type of the state,

@@ -836,7 +836,7 @@ __device__ __forceinline__ double centre_norm2(LayerShared<S, T>& sh, int Dl, in
 // True when layer `layer` of the CNOT-ladder circuit keeps every singular value at every bond:
 // the bond rule gives D_k = min(rows, cols) of each two-site matrix, so no weight can be
 // discarded and the split of each bond is exact whatever factorisation is used.
-__device__ __forceinline__ bool layer_keeps_all(int n, int chi, int layer) {
+__host__ __device__ inline bool layer_keeps_all(int n, int chi, int layer) {
   for (int k = 0; k <= n - 2; ++k) {
     const int M = 2 * bond_dim(n, chi, layer + 1, k - 1), N = 2 * bond_dim(n, chi, layer, k + 1);
     if (bond_dim(n, chi, layer + 1, k) != (M < N ? M : N)) return false;
@@ -929,6 +929,245 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
   return flags;
 }
 
+// ----------------------------------------------------------------- exact layers as one contraction
+// The CNOT ladder CNOT(n-2, n-1) ... CNOT(0, 1) maps |x_0 x_1 ...> to |y_0 y_1 ...> with
+// y_k = x_0 XOR ... XOR x_k, a matrix product operator of bond dimension 2 whose bond carries
+// the running parity: site k reads the parity p of its left bond, emits y = x XOR p and passes
+// q = y on.  With the one-qubit gate U_k in front, the exact layer on the MPS is, site by site,
+//   B[k][(p,a), y, (q,b)] = (U_k A[k])[a, y XOR p, b] * delta(q, y)
+// (no p at site 0, no q at site n-1), a tensor of bonds 2 D^old: nothing couples two sites.
+// Where the bond rule keeps D_k < 2 D_k^old the doubled bond is reduced exactly at the chain
+// ends: on a prefix of bonds with D_k = 2 D_{k-1} the sites become identities
+// (A[k][a, s, 2a+s] = 1) and the product of the B's is carried into the next site; on a suffix
+// with D_k = 2 D_{k+1} the sites become identities A[k][s D_k + b, s, b] = 1 and the product is
+// carried left.  Every bond between keeps D_k = 2 D_k^old.
+constexpr int kXcds = 8;
+
+struct MpoPlan {
+  int kl, kr;  // bonds 0..kl reduced from the left, kr..n-2 from the right
+};
+
+// True when the bond rule of the layer has that shape (which holds exactly when the layer
+// keeps every singular value); fills the two ends.
+template <typename Before, typename After>
+__host__ __device__ inline bool mpo_plan(int n, Before dold, After dnew, MpoPlan& p) {
+  int kl = -1;
+  while (kl + 1 <= n - 2 && dnew(kl + 1) < 2 * dold(kl + 1) && dnew(kl + 1) == 2 * dnew(kl)) ++kl;
+  int kr = n - 1;
+  while (kr - 1 > kl && dnew(kr - 1) < 2 * dold(kr - 1) && dnew(kr - 1) == 2 * dnew(kr)) --kr;
+  for (int k = kl + 1; k < kr; ++k)
+    if (dnew(k) != 2 * dold(k)) return false;
+  p.kl = kl;
+  p.kr = kr;
+  return true;
+}
+
+// (U A)[a, t, b] of an old site tensor read through at(a, s, b).
+template <typename At>
+__device__ __forceinline__ cd gated_at(const At& at, const Gate2& g, int a, int t, int b) {
+  const cd v0 = at(a, 0, b), v1 = at(a, 1, b);
+  cd w = cmul(t ? g.u10 : g.u00, v0);
+  cfma(w, t ? g.u11 : g.u01, v1);
+  return w;
+}
+
+__device__ __forceinline__ bool finite_c(cd v) { return isfinite(v.re) && isfinite(v.im); }
+
+// A site between the reduced ends: A[k] <- B[k] (bonds 2 Dp x 2 x 2 Do), written to `slot` by
+// `nthreads` lanes; the old tensor is read through `at` from a staged copy, so the slot may be
+// overwritten.  Returns true if a value is not finite.
+template <int S, typename T, typename At>
+__device__ __forceinline__ bool mpo_plain_site(const At& at, const Gate2& g, int Dp, int Do, T* slot,
+                                               int lane, int nthreads) {
+  bool bad = false;
+  const int R = 2 * Do;
+  const FastDiv fr(R), fdp(Dp), fdo(Do);
+  for (int idx = lane; idx < 4 * Dp * R; idx += nthreads) {
+    const int row = fr.q(idx), m = fr.r(idx), i = row >> 1, y = row & 1;
+    const int p = fdp.q(i), a = fdp.r(i), q = fdo.q(m), b = fdo.r(m);
+    const cd v = (q == y) ? gated_at(at, g, a, y ^ p, b) : cd{0.0, 0.0};
+    bad |= !finite_c(v);
+    store_c<T, double>(slot, (size_t)row * S + m, v);
+  }
+  return bad;
+}
+
+// The reduced ends and the sites that receive their carries (FP64 carries in LDS):
+//  part 0: the left end, and the right end too when both carries land on one site;
+//  part 1: the right end (nothing when both carries land on one site);
+//  part 2: both ends.
+// The next site's load overlaps each carry step, and the identity tensors are stored after the
+// last load, so that no step waits for earlier stores.  Returns true if a value is not finite.
+template <int S, typename T, typename Before, typename After>
+__device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After dnew,
+                         const MpoPlan& plan, const double* theta, const double* phi,
+                         SitePrefetch<S, T>& pf, int part) {
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  constexpr int CS = 2 * S;  // row stride of the left carry (columns <= 2 S)
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x, kl = plan.kl, kr = plan.kr;
+  const bool meet = kl + 1 == kr;
+  if (part == 1 && meet) return false;
+  const bool do_left = part != 1, do_right = part != 0 || meet;
+  // MPO bond size on the left of site k: 2 D_{k-1}^old (1 at site 0).
+  auto lm = [&](int k) { return k == 0 ? 1 : 2 * dold(k - 1); };
+  auto at = [&](int a, int s_, int b) { return to_cd(sh.tb[(a * 2 + s_) * SP + b]); };
+  // Visiting order: left chain 0..kl, right chain n-1..kr+1, then the carry sites.
+  const int nl = do_left ? kl + 1 : 0, nr = do_right ? n - 1 - kr : 0;
+  const bool two = do_left && do_right && !meet;
+  const int total = nl + nr + (two ? 2 : 1);
+  auto site_at = [&](int t) {
+    if (t < nl) return t;
+    if (t < nl + nr) return n - 1 - (t - nl);
+    return (t == nl + nr && do_left) ? kl + 1 : kr;
+  };
+  cd* cbuf[2] = {sh.mat, sh.mat + S * CS};
+  cd* rbuf[2] = {sh.uq, sh.ta};
+  int cur = 0, rcur = 0;
+  if (tid == 0) {
+    cbuf[0][0] = cd{1.0, 0.0};
+    rbuf[0][0] = cd{1.0, 0.0};
+  }
+  bool bad = false;
+  pf.load(st + (size_t)site_at(0) * SLOT, dold(site_at(0) - 1), dold(site_at(0)));
+  for (int t = 0; t < total; ++t) {
+    const int k = site_at(t);
+    pf.commit(sh.tb);
+    __syncthreads();
+    if (t + 1 < total) {
+      const int kn = site_at(t + 1);
+      pf.load(st + (size_t)kn * SLOT, dold(kn - 1), dold(kn));
+    }
+    const Gate2 g = site_gate(kGateRyRz, k, theta, phi, nullptr);
+    const int Dp = dold(k - 1), Do = dold(k), L = lm(k);
+    const FastDiv fdp(Dp), fdo(Do);
+    if (t < nl) {
+      // C_k[2a+s][(q,b)] = delta(q,s) sum_i C_{k-1}[a][i] B[k][i, s, (s,b)]
+      const int rows = dnew(k - 1), R = 2 * Do;
+      const FastDiv fr(R);
+      const cd* C = cbuf[cur];
+      cd* Cn = cbuf[cur ^ 1];
+      for (int idx = tid; idx < rows * 2 * R; idx += kLayerThreads) {
+        const int row = fr.q(idx), m = fr.r(idx), a = row >> 1, s_ = row & 1;
+        const int q = fdo.q(m), b = fdo.r(m);
+        cd acc{0.0, 0.0};
+        if (q == s_)
+          for (int i = 0; i < L; ++i) cfma(acc, C[a * CS + i], gated_at(at, g, fdp.r(i), s_ ^ fdp.q(i), b));
+        Cn[row * CS + m] = acc;
+      }
+      cur ^= 1;
+    } else if (t < nl + nr) {
+      // R_k[i][s D_k + b] = sum_b' B[k][i, s, (s,b')] R_{k+1}[(s,b')][b]
+      const int Dn = dnew(k), cols = 2 * Dn;
+      const FastDiv fc(cols), fdn(Dn);
+      const cd* Rk = rbuf[rcur];
+      cd* Rn = rbuf[rcur ^ 1];
+      for (int idx = tid; idx < L * cols; idx += kLayerThreads) {
+        const int i = fc.q(idx), f = fc.r(idx), s_ = fdn.q(f), b = fdn.r(f);
+        const int p = fdp.q(i), a = fdp.r(i);
+        cd acc{0.0, 0.0};
+        for (int bp = 0; bp < Do; ++bp) {
+          const int mrow = (k == n - 1) ? bp : s_ * Do + bp;
+          cfma(acc, gated_at(at, g, a, s_ ^ p, bp), Rk[mrow * S + b]);
+        }
+        Rn[i * S + f] = acc;
+      }
+      rcur ^= 1;
+    } else {
+      // a carry site: C B[k] when k = kl+1 (left end), B[k] R when k = kr (right end)
+      const bool lc = do_left && k == kl + 1, rc = do_right && k == kr;
+      const cd* C = cbuf[cur];
+      const cd* Rc = rbuf[rcur];
+      cd* V = sh.mat + (cur ^ 1) * S * CS;  // free half of mat: [D_kl][2][D_k^old]
+      const int rows = lc ? dnew(kl) : L;
+      if (lc) {
+        // V[a'][y][b'] = sum_i C[a'][i] (U A)[a(i), y XOR p(i), b']
+        const FastDiv f2o(2 * Do);
+        for (int idx = tid; idx < rows * 2 * Do; idx += kLayerThreads) {
+          const int an = f2o.q(idx), r2 = f2o.r(idx), y = fdo.q(r2), bp = fdo.r(r2);
+          cd acc{0.0, 0.0};
+          for (int i = 0; i < L; ++i) cfma(acc, C[an * CS + i], gated_at(at, g, fdp.r(i), y ^ fdp.q(i), bp));
+          V[idx] = acc;
+        }
+        __syncthreads();
+      }
+      // left factor of row (r, y) at b': V (carried) or (U A)[a, y XOR p, b'] (plain)
+      auto left = [&](int r, int y, int bp) -> cd {
+        return lc ? V[(r * 2 + y) * Do + bp] : gated_at(at, g, fdp.r(r), y ^ fdp.q(r), bp);
+      };
+      T* slot = st + (size_t)k * SLOT;
+      if (rc) {
+        const int cols = dnew(kr);
+        const FastDiv fc(cols);
+        for (int idx = tid; idx < rows * 2 * cols; idx += kLayerThreads) {
+          const int row = fc.q(idx), j = fc.r(idx), r = row >> 1, y = row & 1;
+          cd acc{0.0, 0.0};
+          for (int bp = 0; bp < Do; ++bp) {
+            const int mrow = (k == n - 1) ? bp : y * Do + bp;
+            cfma(acc, left(r, y, bp), Rc[mrow * S + j]);
+          }
+          bad |= !finite_c(acc);
+          store_c<T, double>(slot, (size_t)row * S + j, acc);
+        }
+      } else {
+        const int R = (k == n - 1) ? 1 : 2 * Do;
+        const FastDiv fr(R);
+        for (int idx = tid; idx < rows * 2 * R; idx += kLayerThreads) {
+          const int row = fr.q(idx), m = fr.r(idx), r = row >> 1, y = row & 1;
+          const int q = fdo.q(m), b = fdo.r(m);
+          const cd v = (k == n - 1 || q == y) ? left(r, y, b) : cd{0.0, 0.0};
+          bad |= !finite_c(v);
+          store_c<T, double>(slot, (size_t)row * S + m, v);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // identity tensors of the reduced sites
+  for (int k = 0; k < nl; ++k) {
+    const int D = dnew(k);
+    for (int idx = tid; idx < D * D; idx += kLayerThreads) {
+      const int row = idx / D, col = idx - row * D;
+      store_c<T, double>(st + (size_t)k * SLOT, (size_t)row * S + col, cd{row == col ? 1.0 : 0.0, 0.0});
+    }
+  }
+  for (int k = n - 1; k > n - 1 - nr; --k) {
+    const int Dn = dnew(k), rows = 4 * Dn;
+    for (int idx = tid; idx < rows * Dn; idx += kLayerThreads) {
+      const int row = idx / Dn, b = idx - row * Dn, j = row >> 1, s_ = row & 1;
+      store_c<T, double>(st + (size_t)k * SLOT, (size_t)row * S + b, cd{j == s_ * Dn + b ? 1.0 : 0.0, 0.0});
+    }
+  }
+  return bad;
+}
+
+// One wavefront applies a whole exact layer: both ends, then the sites between.  The result is
+// the exact state (up to rounding) in the gauge of the contraction: no site is orthonormalised
+// and the norm is the input's (the layer is unitary); trunc_err is 0.
+template <int S, typename T, typename Before, typename After>
+__device__ int mpo_layer(LayerShared<S, T>& sh, T* st, int n, Before dold, After dnew,
+                         const MpoPlan& plan, const double* theta, const double* phi,
+                         double* trunc_err, SitePrefetch<S, T>& pf) {
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x;
+  if (trunc_err)
+    for (int k = tid; k < n - 1; k += kLayerThreads) trunc_err[k] = 0.0;
+  bool bad = mpo_ends<S, T>(sh, st, n, dold, dnew, plan, theta, phi, pf, 2);
+  auto at = [&](int a, int s_, int b) { return to_cd(sh.tb[(a * 2 + s_) * SP + b]); };
+  const int k0 = plan.kl + 2, k1 = plan.kr - 1;
+  if (k0 <= k1) pf.load(st + (size_t)k0 * SLOT, dold(k0 - 1), dold(k0));
+  for (int k = k0; k <= k1; ++k) {
+    pf.commit(sh.tb);
+    __syncthreads();
+    if (k + 1 <= k1) pf.load(st + (size_t)(k + 1) * SLOT, dold(k), dold(k + 1));
+    bad |= mpo_plain_site<S, T>(at, site_gate(kGateRyRz, k, theta, phi, nullptr), dold(k - 1),
+                                dold(k), st + (size_t)k * SLOT, tid, kLayerThreads);
+    __syncthreads();
+  }
+  return __any(bad) ? kImgNonfinite : 0;
+}
+
 // Applies layer `layer` (0-based) to one image whose n slots start at `st`.
 //  program kLayerRyRzLadder: R_Y(theta_k) R_Z(phi_k) on every site, then CNOT(k, k+1) for
 //    k = 0..n-2 in order: one canonical sweep and one CNOT sweep.
@@ -954,7 +1193,11 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     flags |= canon_sweep<S, T>(sh, st, n, dmid, kGateNone, theta, phi, pix, true, pf);
     flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf, exact_qr);
   } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
-    flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
+    MpoPlan plan;
+    if (exact_qr == kExactMpo && mpo_plan(n, dold, dnew, plan))
+      flags |= mpo_layer<S, T>(sh, st, n, dold, dnew, plan, theta, phi, trunc_err, pf);
+    else
+      flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
   } else {
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateRyRz, theta, phi, pix, false, pf);
     flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf, exact_qr);
@@ -976,11 +1219,62 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
                     trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b, exact_qr);
 }
 
-// Host-side policy for ladder layers that keep every singular value (1: QR sweep, 0: canonical
-// sweep + Jacobi SVD ladder like every other layer), read at each launch.
-int g_exact_qr = 1;
+// A layer that keeps every singular value, batched: the ends (two workgroups per image, the
+// left and the right end) and the sites between (one workgroup per site) run as two launches
+// over disjoint sites.  All workgroups of image b sit on XCD b % 8, like the other kernels.
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_mpo_ends(T* state, int n, int chi, int layer,
+                                                            MpoPlan plan, const double* theta,
+                                                            const double* phi, double* trunc_err,
+                                                            int* status, int batch) {
+  __shared__ LayerShared<S, T> sh;
+  const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
+  const int b = kXcds * (j >> 1) + xcd, part = j & 1;
+  if (b >= batch) return;
+  auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
+  auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
+  if (part == 0 && trunc_err)
+    for (int k = threadIdx.x; k < n - 1; k += kLayerThreads) trunc_err[(size_t)b * (n - 1) + k] = 0.0;
+  SitePrefetch<S, T> pf;
+  const bool bad = mpo_ends<S, T>(sh, state + (size_t)b * n * ((size_t)2 * S * S * 2), n, dold,
+                                  dnew, plan, theta, phi, pf, part);
+  if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
+}
 
-void set_exact_qr(int on) { g_exact_qr = on ? 1 : 0; }
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_mpo_sites(T* state, int n, int chi, int layer,
+                                                             MpoPlan plan, const double* theta,
+                                                             const double* phi, int* status,
+                                                             int batch) {
+  // a site between the ends has old bonds D^old = D / 2 <= S / 2
+  constexpr int H = S / 2 > 0 ? S / 2 : 1;
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  __shared__ cx<T> old[H * 2 * H];
+  const int nmid = plan.kr - plan.kl - 2;
+  const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
+  const int b = kXcds * (j / nmid) + xcd, k = plan.kl + 2 + j % nmid;
+  if (b >= batch) return;
+  const int Dp = bond_dim(n, chi, layer, k - 1), Do = bond_dim(n, chi, layer, k);
+  T* slot = state + ((size_t)b * n + k) * SLOT;
+  const FastDiv fdo(Do);
+  for (int idx = threadIdx.x; idx < Dp * 2 * Do; idx += kLayerThreads) {
+    const int row = fdo.q(idx), c = fdo.r(idx);
+    old[idx] = cx<T>{slot[2 * ((size_t)row * S + c)], slot[2 * ((size_t)row * S + c) + 1]};
+  }
+  __syncthreads();
+  auto at = [&](int a, int s_, int c) { return to_cd(old[(a * 2 + s_) * Do + c]); };
+  const bool bad = mpo_plain_site<S, T>(at, site_gate(kGateRyRz, k, theta, phi, nullptr), Dp, Do,
+                                        slot, threadIdx.x, kLayerThreads);
+  if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
+}
+
+// Host-side policy for bonds and layers that keep every singular value (kExactMpo: whole
+// ladder layers as one contraction, other such bonds split exactly; kExactQr: such layers by
+// the QR sweep; kExactSvd: canonical sweep + Jacobi SVD ladder like every other layer), read
+// at each launch.
+int g_exact_qr = kExactMpo;
+
+void set_exact_qr(int mode) { g_exact_qr = mode; }
 int exact_qr() { return g_exact_qr; }
 
 // ------------------------------------------------------------------------------- mixed requests
@@ -1123,6 +1417,27 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
                         const double* theta, const double* phi, const double* pixels,
                         double* trunc_err, int* status, hipStream_t stream) {
   const dim3 grid(batch), block(kLayerThreads);
+  MpoPlan plan;
+  if (program == kLayerRyRzLadder && g_exact_qr == kExactMpo && layer_keeps_all(n, chi, layer) &&
+      mpo_plan(n, [&](int k) { return bond_dim(n, chi, layer, k); },
+               [&](int k) { return bond_dim(n, chi, layer + 1, k); }, plan)) {
+    const unsigned groups = (unsigned)((batch + kXcds - 1) / kXcds);
+    const int nmid = plan.kr - plan.kl - 2;
+    switch (S) {
+#define ANOMPS_KM(SV)                                                                              \
+  case SV:                                                                                         \
+    hipLaunchKernelGGL((k_mpo_ends<SV, T>), dim3(kXcds * groups * 2), block, 0, stream, state, n,  \
+                       chi, layer, plan, theta, phi, trunc_err, status, batch);                    \
+    if (nmid > 0)                                                                                  \
+      hipLaunchKernelGGL((k_mpo_sites<SV, T>), dim3(kXcds * groups * (unsigned)nmid), block, 0,    \
+                         stream, state, n, chi, layer, plan, theta, phi, status, batch);           \
+    break;
+      ANOMPS_KM(2) ANOMPS_KM(4) ANOMPS_KM(8) ANOMPS_KM(16)
+#undef ANOMPS_KM
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (S) {
 #define ANOMPS_KL(SV)                                                                              \
   case SV:                                                                                         \

@@ -349,13 +349,11 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
     for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{a1[kc].re, -a1[kc].im};
     cgemm<SPLIT>(x, lo, ac);
     acc_as_b(x, x1);
-    Acc f00 = acc_zero(), f01 = acc_zero(), f11 = acc_zero();
+    Acc f00 = acc_zero(), f01 = acc_zero();
     cgemm<SPLIT>(f00, a0, x0);
     cgemm<SPLIT>(f01, a0, x1);
-    cgemm<SPLIT>(f11, a1, x1);
     st_acc(F[0], f00);
     st_acc(F[1], f01);
-    st_acc(F[2], f11);
   }
   __syncthreads();
   int cur = i + 1;
@@ -367,19 +365,29 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
       cf a0[4], a1[4], e[4];
       ld_colop(at, a0, false);
       ld_colop(at + 16 * TS, a1, false);
-      Acc nf[3];
+      Acc nf[2];
 #pragma unroll
-      for (int blk = 0; blk < 3; ++blk) {
+      for (int blk = 0; blk < 2; ++blk) {
         ld_rowop(F[blk], e, false);
         nf[blk] = left_transfer<SPLIT>(e, a0, a1);
       }
       __syncthreads();
 #pragma unroll
-      for (int blk = 0; blk < 3; ++blk) st_acc(F[blk], nf[blk]);
+      for (int blk = 0; blk < 2; ++blk) st_acc(F[blk], nf[blk]);
       __syncthreads();
     }
     // ---- close at j: Y_t' = R A_t'^H ; G^{tt'} = A_t Y_t'
     env_to_lds(Ev, evR + (size_t)(j + 1) * ETILE);
+    // F^{11} = L_j - F^{00}: the two diagonal blocks of the open index sum to the left
+    // environment of site j, so only F^{00} and F^{01} are carried through the sites between.
+    {
+      const float* lj = evL + (size_t)j * ETILE;
+      for (int idx = l; idx < 256; idx += W) {
+        const int r = idx >> 4, c = idx & 15;
+        const cf f0 = F[0][r * TS + c];
+        F[2][r * TS + c] = cf{lj[2 * idx] - f0.re, lj[2 * idx + 1] - f0.im};
+      }
+    }
     need(j);
     __syncthreads();
     Acc G[3];

@@ -33,6 +33,24 @@ def layer_keeps_all(n: int, chi: int, layer: int) -> bool:
                for k in range(n - 1))
 
 
+def mpo_plan(n: int, chi: int, layer: int):
+    """Chain ends of a layer applied as the parity product operator: bonds 0..kl are reduced
+    from the left (D_k = 2 D_{k-1} < 2 D_k^old), bonds kr..n-2 from the right
+    (D_k = 2 D_{k+1} < 2 D_k^old), every bond between keeps D_k = 2 D_k^old.  None when the bond
+    rule has another shape (exactly when the layer does not keep every singular value)."""
+    do = lambda k: bond(n, chi, layer, k)
+    dn = lambda k: bond(n, chi, layer + 1, k)
+    kl = -1
+    while kl + 1 <= n - 2 and dn(kl + 1) < 2 * do(kl + 1) and dn(kl + 1) == 2 * dn(kl):
+        kl += 1
+    kr = n - 1
+    while kr - 1 > kl and dn(kr - 1) < 2 * do(kr - 1) and dn(kr - 1) == 2 * dn(kr):
+        kr -= 1
+    if any(dn(k) != 2 * do(k) for k in range(kl + 1, kr)):
+        return None
+    return kl, kr
+
+
 def householder_qr_flops(m: int, n: int) -> float:
     """Complex Householder QR of an m x n matrix (m >= n) with Q formed explicitly: each
     reflector costs a dot product and an update over the remaining columns and rows, once to
@@ -40,16 +58,33 @@ def householder_qr_flops(m: int, n: int) -> float:
     return CMAC * 4.0 * sum((n - j) * (m - j) for j in range(n))
 
 
-def layer_flops(n: int, chi: int, layer: int, exact_qr: bool = True) -> dict:
-    """Work of applying layer `layer` (0-based) to one image.  A layer that keeps every singular
-    value (and exact_qr) is one sweep: gate the neighbour, then split each bond exactly -- through
-    two Householder blocks of the centre when D = 2 D_old (no two-site matrix), else contract
-    Theta' and split it by Householder QR (or not at all when D equals its row count).  Otherwise: canonical sweep
-    (gate + SVD of each site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left
-    neighbour), then the ladder (two-site contraction, SVD, U^H Theta' for the new centre)."""
+def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo") -> dict:
+    """Work of applying layer `layer` (0-based) to one image.  mode "mpo" (a layer that keeps
+    every singular value, applied as the parity product operator): the gate on every old
+    tensor, the left and right carries over the reduced chain ends and their product into the
+    first full sites.  mode "qr" (such a layer in one sweep): gate the neighbour, then split
+    each bond exactly -- through two Householder blocks of the centre when D = 2 D_old (no
+    two-site matrix), else contract Theta' and split it by Householder QR (or not at all when D
+    equals its row count).  Otherwise, and for mode "svd": canonical sweep (gate + SVD of each
+    site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left neighbour), then the ladder
+    (two-site contraction, SVD, U^H Theta' for the new centre)."""
     d_old = lambda k: bond(n, chi, layer, k)
     d_new = lambda k: bond(n, chi, layer + 1, k)
-    if exact_qr and layer_keeps_all(n, chi, layer):
+    plan = mpo_plan(n, chi, layer) if mode == "mpo" else None
+    if plan is not None:
+        kl, kr = plan
+        lm = lambda k: 1 if k == 0 else 2 * d_old(k - 1)
+        gate = sum(CMAC * 4 * d_old(k - 1) * d_old(k) for k in range(n))
+        carry = 0.0
+        for k in range(kl + 1):          # C_k = C_{k-1} B[k] (one parity block per row)
+            carry += CMAC * d_new(k) * d_old(k) * lm(k)
+        for k in range(n - 1, kr, -1):   # R_k = B[k] R_{k+1}
+            carry += CMAC * lm(k) * 2 * d_new(k) * d_old(k)
+        carry += CMAC * d_new(kl) * 2 * d_old(kl + 1) * lm(kl + 1)   # C B at site kl+1
+        carry += CMAC * d_new(kr - 1) * 2 * d_new(kr) * d_old(kr)    # (C) B R at site kr
+        return {"qr_fp64": 0.0, "svd_fp64": 0.0, "other_fp64": gate + carry,
+                "total_fp64": gate + carry}
+    if mode in ("mpo", "qr") and layer_keeps_all(n, chi, layer):
         qr = other = 0.0
         other += CMAC * 4 * d_old(0)
         for k in range(n - 1):
@@ -90,7 +125,9 @@ def env_flops(n: int, chi: int, layers: int) -> float:
 
 
 def pair_flops(n: int, chi: int, layers: int, pairs) -> float:
-    """Open at i, carry through i+1..j-1 (shared by all partners of i), close at each j."""
+    """Open at i, carry through i+1..j-1 (shared by all partners of i), close at each j.  Only
+    the blocks F^00 and F^01 of the open index are carried: F^11 = L_j - F^00 at the close,
+    since the two diagonal blocks sum to the left environment."""
     d = lambda k: bond(n, chi, layers, k)
     by_start: dict = {}
     for i, j in pairs:
@@ -98,10 +135,10 @@ def pair_flops(n: int, chi: int, layers: int, pairs) -> float:
     total = 0
     for i, js in by_start.items():
         dl, dc = d(i - 1), d(i)
-        total += 2 * dl * dc * dl + 3 * dc * dc * dl
+        total += 2 * dl * dc * dl + 2 * dc * dc * dl
         for k in range(i + 1, max(js)):
             a, b = d(k - 1), d(k)
-            total += 6 * a * b * a + 3 * b * b * 2 * a
+            total += 4 * a * b * a + 2 * b * b * 2 * a
         for j in js:
             dd, dj = d(j - 1), d(j)
             total += 2 * dj * dd * dj + 3 * dd * dd * dj + 16 * dd * dd
@@ -114,10 +151,11 @@ def state_bytes(n: int, chi: int, layers: int, real_bytes: int) -> int:
                for k in range(n))
 
 
-def layer_bytes(n: int, chi: int, layer: int, real_bytes: int, exact_qr: bool = True) -> int:
+def layer_bytes(n: int, chi: int, layer: int, real_bytes: int, mode: str = "mpo") -> int:
     """HBM traffic of one layer for one image: the canonical sweep reads and writes every
-    tensor once, the ladder reads and writes every tensor once; a layer split by QR in one sweep
-    reads the old tensors once and writes the new ones once."""
-    if exact_qr and layer_keeps_all(n, chi, layer):
+    tensor once, the ladder reads and writes every tensor once; a layer that keeps every
+    singular value (modes "mpo" and "qr") reads the old tensors once and writes the new ones
+    once."""
+    if mode in ("mpo", "qr") and layer_keeps_all(n, chi, layer):
         return state_bytes(n, chi, layer, real_bytes) + state_bytes(n, chi, layer + 1, real_bytes)
     return 2 * state_bytes(n, chi, layer, real_bytes) + 2 * state_bytes(n, chi, layer + 1, real_bytes)

@@ -78,9 +78,11 @@ def test_wide_slot_sizes():
 def test_exact_layer_policy_arguments():
     anomps.set_exact_layers(anomps.EXACT_SVD)
     anomps.set_exact_layers(anomps.EXACT_QR)
-    with pytest.raises(anomps.MpsError) as e:
-        anomps.set_exact_layers(2)
-    assert e.value.code == -1
+    anomps.set_exact_layers(anomps.EXACT_MPO)
+    for bad in (3, -1):
+        with pytest.raises(anomps.MpsError) as e:
+            anomps.set_exact_layers(bad)
+        assert e.value.code == -1
 
 
 def test_validate_pairs():

@@ -133,26 +133,33 @@ def test_49q_grid_fp32(A, L, chi):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_exact_layers_qr_matches_svd(A, prec):
-    """chi = 16 = 2^L keeps every singular value, so each layer runs the one-sweep QR split by
-    default; forcing the canonical sweep + Jacobi SVD ladder gives the same features, both
-    match the oracle, and the QR path reports zero discarded weight."""
+def test_exact_layer_modes_agree(A, prec):
+    """chi = 16 = 2^L keeps every singular value, so each layer is applied by default as the
+    parity product operator site by site; the one-sweep QR split and the canonical sweep +
+    Jacobi SVD ladder give the same features, all three match the oracle, and the two exact
+    modes report zero discarded weight."""
     p, n, B, L, chi = 7, 49, 4, 4, 16
     x = inputs.blob_images(B, p, 500)
     th, ph = inputs.layer_angles(L, n, 501)
     pairs = inputs.neighbour_pairs(p)
-    A.set_exact_layers(A.EXACT_SVD)
+    res = {}
     try:
-        svd, st_svd, te_svd = run(A, x, th, ph, pairs, chi, prec, trunc=True)
+        for mode in (A.EXACT_SVD, A.EXACT_QR, A.EXACT_MPO):
+            A.set_exact_layers(mode)
+            res[mode] = run(A, x, th, ph, pairs, chi, prec, trunc=True)
     finally:
-        A.set_exact_layers(A.EXACT_QR)
-    qr, st_qr, te_qr = run(A, x, th, ph, pairs, chi, prec, trunc=True)
+        A.set_exact_layers(A.EXACT_MPO)
     ref = ofeat.exact_features(x[:2], th, ph, pairs)
     tol = FP64_TOL if prec == A.PREC_FP64 else FP32_TOL
-    assert np.all(st_svd == 0) and np.all(st_qr == 0)
-    assert np.all(te_qr == 0.0) and te_svd.max() < 1e-20
-    assert np.abs(qr - svd).max() <= tol
-    assert np.abs(qr[:2] - ref).max() <= tol and np.abs(svd[:2] - ref).max() <= tol
+    svd = res[A.EXACT_SVD][0]
+    for mode, (out, status, terr) in res.items():
+        assert np.all(status == 0), mode
+        if mode == A.EXACT_SVD:
+            assert terr.max() < 1e-20
+        else:
+            assert np.all(terr == 0.0), mode
+        assert np.abs(out - svd).max() <= tol, mode
+        assert np.abs(out[:2] - ref).max() <= tol, mode
 
 
 # ------------------------------------------------------------------ edge cases

@@ -74,7 +74,26 @@ def test_layers_that_keep_every_singular_value():
     n, chi, l, k = 49, 8, 3, 20
     D = w.bond(n, chi, l + 1, k)
     assert D == 8 and min(2 * w.bond(n, chi, l + 1, k - 1), 2 * w.bond(n, chi, l, k + 1)) == 16
-    # the QR path is priced below the SVD path and reads/writes each tensor once
-    f_qr, f_svd = w.layer_flops(49, 16, 3), w.layer_flops(49, 16, 3, exact_qr=False)
+    # the exact paths are priced below the SVD path and read/write each tensor once
+    f_mpo, f_qr, f_svd = (w.layer_flops(49, 16, 3, m) for m in ("mpo", "qr", "svd"))
     assert f_qr["svd_fp64"] == 0 and 0 < f_qr["total_fp64"] < f_svd["total_fp64"]
+    assert 0 < f_mpo["total_fp64"] < f_qr["total_fp64"]
     assert w.layer_bytes(49, 16, 3, 4) == w.state_bytes(49, 16, 3, 4) + w.state_bytes(49, 16, 4, 4)
+
+
+def test_product_operator_plan():
+    """The site-by-site form of an exact layer applies exactly when the layer keeps every
+    singular value; its reduced ends at 7x7, chi = 16 are the bonds whose rule dimension is
+    the full left (2^(k+1)) or right (2^(n-k-1)) space."""
+    from paper_2607_10280_amd import workload as w
+    for n in range(2, 40):
+        for chi in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128):
+            for layer in range(8):
+                assert (w.mpo_plan(n, chi, layer) is not None) == w.layer_keeps_all(n, chi, layer)
+    assert [w.mpo_plan(49, 16, l) for l in range(4)] == [(-1, 48), (0, 47), (1, 46), (2, 45)]
+    kl, kr = w.mpo_plan(49, 16, 3)
+    assert all(w.bond(49, 16, 4, k) == 2 ** (k + 1) for k in range(kl + 1))
+    assert all(w.bond(49, 16, 4, k) == 2 ** (49 - k - 1) for k in range(kr, 48))
+    assert all(w.bond(49, 16, 4, k) == 2 * w.bond(49, 16, 3, k) for k in range(kl + 1, kr))
+    # a short chain whose two reduced ends meet at one site
+    assert w.mpo_plan(4, 16, 3) == (1, 2)
