@@ -33,13 +33,15 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0,
 # the factors a 1 GiB device copy reads), valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
+    # one layer call, averaged over the four layers of the workload: k_mpo_ends + k_mpo_sites
     "layer": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-              "sha1": "a78cbff4a2b616629735c1221410f46758e1302a",
-              "bytes": (2 * 22727.5 + 59776.8) * 1024},
+              "sha1": "8cc5138f1c1a9de973cf5a1252871156e4445f6b",
+              "bytes": ((2 * 42037.1 + 167936.0) + (2 * 22068.5 + 44032.0) + (2 * 11572.5 + 11520.0)
+                        + (2 * 6068.5 + 6016.0) + 4 * (2 * 2175.6 + 2016.0)) / 4 * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "0473b8e9612fd853869a6e4a849b87bbf81aaaf0",
-                "bytes": (2 * (173292.0 + 274482.7) + (204800.0 + 294760.6)) * 1024},
+                "sha1": "ea0c34a60e032bda24de21e4cd0d4a1dbacc1bde",
+                "bytes": (2 * (194884.7 + 234909.5) + (204807.8 + 5897.5)) * 1024},
 }
 
 

@@ -11,7 +11,10 @@
 //   A-operand value  A[l%16][4g+kc],   B-operand value  B[4g+kc][l%16],
 // and owns accumulator entries D[4g+r][l%16], r = 0..3.  Because the accumulator layout equals
 // the B-operand layout (chunk kc <-> entry r), a product can feed the right factor of the next
-// product directly from registers.  Tiles are zero padded to 16 when a bond is narrower.
+// product directly from registers; an accumulator holding M^T is the A-operand of M, so
+// environments and carried blocks are kept transposed and no product goes through LDS.  Site
+// tiles are read from memory straight into operand registers, one step ahead.  Tiles are zero
+// padded to 16 when a bond is narrower.
 //
 // Work mapping is XCD-aware: workgroup w runs on XCD w % 8, so all workgroups of image b are
 // placed on XCD b % 8 (the same XCD that ran the layer kernels of image b), keeping its tensors
@@ -26,7 +29,6 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 using cf = cx<float>;
 constexpr int W = 64;        // one wavefront per workgroup
-constexpr int TS = 17;       // LDS row stride of a 16x16 complex tile (bank-conflict padding)
 constexpr int NXCD = 8;
 constexpr int kMaxTargets16 = 256;
 
@@ -113,75 +115,64 @@ __device__ __forceinline__ void acc_as_b(const Acc& c, cf (&b)[4]) {
   for (int r = 0; r < 4; ++r) b[r] = cf{c.re[r], c.im[r]};
 }
 
-// Operand loads from a 16x16 LDS tile (row stride TS).
-__device__ __forceinline__ void ld_rowop(const cf* t, cf (&v)[4], bool conj_) {  // t[l%16][4g+kc]
-  const int l = threadIdx.x, i = l & 15, g = l >> 4;
-#pragma unroll
-  for (int kc = 0; kc < 4; ++kc) {
-    cf x = t[i * TS + 4 * g + kc];
-    v[kc] = conj_ ? cf{x.re, -x.im} : x;
-  }
-}
-__device__ __forceinline__ void ld_colop(const cf* t, cf (&v)[4], bool conj_) {  // t[4g+kc][l%16]
-  const int l = threadIdx.x, j = l & 15, g = l >> 4;
-#pragma unroll
-  for (int kc = 0; kc < 4; ++kc) {
-    cf x = t[(4 * g + kc) * TS + j];
-    v[kc] = conj_ ? cf{x.re, -x.im} : x;
-  }
-}
-__device__ __forceinline__ void st_acc(cf* t, const Acc& c) {  // t[4g+r][l%16] = acc
-  const int l = threadIdx.x, j = l & 15, g = l >> 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) t[(4 * g + r) * TS + j] = cf{c.re[r], c.im[r]};
-}
-
-// Site tensor (Dl x 2 x Dr, slot stride 16) -> two zero-padded 16x16 tiles at[u][c][e].
-struct SiteRegs {
-  cf v[8];
-  __device__ void load(const float* slot, int Dl, int Dr) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int idx = threadIdx.x + i * W;  // idx = (c*2+u)*16 + e
-      const int c = idx >> 5, e = idx & 15;
-      v[i] = (c < Dl && e < Dr) ? cf{slot[2 * idx], slot[2 * idx + 1]} : cf{0.f, 0.f};
-    }
-  }
-  __device__ void commit(cf* at) const {  // at[u*16*TS + c*TS + e]
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int idx = threadIdx.x + i * W;
-      const int c = idx >> 5, u = (idx >> 4) & 1, e = idx & 15;
-      at[u * 16 * TS + c * TS + e] = v[i];
-    }
-  }
-};
-
-// Env tile (16x16, stride 16 in HBM) <-> LDS tile.
-__device__ __forceinline__ void env_to_lds(cf* t, const float* src) {
-  for (int idx = threadIdx.x; idx < 256; idx += W) t[(idx >> 4) * TS + (idx & 15)] = cf{src[2 * idx], src[2 * idx + 1]};
-}
-
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
-// X_u = E conj(A_u); E' = sum_u A_u^T X_u   (left transfer of one block E held as A-operand)
+// Operand registers of the two physical slices of a site tensor (Dl x 2 x Dr, slot stride 16),
+// zero outside the Dl x Dr corner:
+//   column form a[u][kc] = A_u[4g+kc][l%16]  (B-operand of A_u, A-operand of A_u^T)
+//   row form    a[u][kc] = A_u[l%16][4g+kc]  (A-operand of A_u, B-operand of A_u^T)
+struct SiteOps {
+  cf a[2][4];
+  __device__ __forceinline__ void load(const float* slot, int Dl, int Dr, bool row) {
+    const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int c = row ? i16 : 4 * g + kc, e = row ? 4 * g + kc : i16;
+        const int idx = (c * 2 + u) * 16 + e;
+        const cf v{slot[2 * idx], slot[2 * idx + 1]};
+        a[u][kc] = (c < Dl && e < Dr) ? v : cf{0.f, 0.f};
+      }
+  }
+};
+
+// Row form (A-operand) of a 16x16 environment tile E[x][y] stored at x*16 + y.
+__device__ __forceinline__ void ld_env_row(const float* t, cf (&v)[4]) {
+  const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const int idx = i16 * 16 + 4 * g + kc;
+    v[kc] = cf{t[2 * idx], t[2 * idx + 1]};
+  }
+}
+
+__device__ __forceinline__ void conj4(const cf (&a)[4], cf (&b)[4]) {
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) b[kc] = cf{a[kc].re, -a[kc].im};
+}
+
+// A matrix M is carried transposed in the accumulator: the lane then holds M^T[4g+r][l%16] =
+// M[l%16][4g+r], which is the A-operand of M, so a chain of products never leaves registers.
+//
+// Left transfer E' = sum_u A_u^T E conj(A_u) with E given as its A-operand (row form):
+// X_u = E conj(A_u), then E'^T = sum_u X_u^T A_u (the accumulator of X_u is the A-operand of
+// X_u^T).  a = column forms of A_0, A_1.  Returns E'^T.
 template <bool SPLIT>
-__device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4], const cf (&a1)[4]) {
+__device__ __forceinline__ Acc left_transfer_t(const cf (&e)[4], const cf (&a)[2][4]) {
   Acc out = acc_zero();
-  cf ac[4], xb[4];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    const cf (&au)[4] = u ? a1 : a0;
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{au[kc].re, -au[kc].im};
+    cf ac[4], xa[4];
+    conj4(a[u], ac);
     Acc x = acc_zero();
     cgemm<SPLIT>(x, e, ac);
-    acc_as_b(x, xb);
-    cgemm<SPLIT>(out, au, xb);
+    acc_as_b(x, xa);
+    cgemm<SPLIT>(out, xa, a[u]);
   }
   return out;
 }
@@ -189,69 +180,56 @@ __device__ __forceinline__ Acc left_transfer(const cf (&e)[4], const cf (&a0)[4]
 }  // namespace
 
 // ------------------------------------------------------------------------- environments
-// One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).
+// One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).  The
+// environment is carried transposed in registers; tiles E[x][y] are stored at x*16 + y.
 template <bool SPLIT>
 __device__ __forceinline__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
-  __shared__ cf at[2 * 16 * TS];
-  __shared__ cf E[16 * TS];
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  const int l = threadIdx.x;
+  const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
-  for (int idx = l; idx < 16 * TS; idx += W) E[idx] = cf{0.f, 0.f};
-  if (l == 0) E[0] = cf{1.f, 0.f};
-  __syncthreads();
+  Acc e = acc_zero();  // the 1 x 1 identity
+  if (l == 0) e.re[0] = 1.f;
   auto store_env = [&](int k) {
     float* dst = ev + (size_t)k * ETILE;
-    for (int idx = l; idx < 256; idx += W) {
-      const cf v = E[(idx >> 4) * TS + (idx & 15)];
-      dst[2 * idx] = v.re;
-      dst[2 * idx + 1] = v.im;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int idx = i16 * 16 + 4 * g + r;
+      dst[2 * idx] = e.re[r];
+      dst[2 * idx + 1] = e.im[r];
     }
   };
-  SiteRegs pf;
-  if (side == 0) {
-    store_env(0);
-    pf.load(st, dim(-1), dim(0));
-    for (int k = 0; k < n; ++k) {
-      pf.commit(at);
-      __syncthreads();
-      if (k + 1 < n) pf.load(st + (size_t)(k + 1) * SLOT, dim(k), dim(k + 1));
-      cf e[4], a0[4], a1[4];
-      ld_rowop(E, e, false);
-      ld_colop(at, a0, false);
-      ld_colop(at + 16 * TS, a1, false);
-      const Acc out = left_transfer<SPLIT>(e, a0, a1);
-      __syncthreads();
-      st_acc(E, out);
-      __syncthreads();
-      store_env(k + 1);
-    }
-  } else {
-    store_env(n);
-    pf.load(st + (size_t)(n - 1) * SLOT, dim(n - 2), dim(n - 1));
-    for (int k = n - 1; k >= 0; --k) {
-      pf.commit(at);
-      __syncthreads();
-      if (k > 0) pf.load(st + (size_t)(k - 1) * SLOT, dim(k - 2), dim(k - 1));
-      // Y_s = R A_s^H ; R' = sum_s A_s Y_s
-      cf r[4], ah[4], as_[4], yb[4];
-      ld_rowop(E, r, false);
-      Acc out = acc_zero();
+  SiteOps cur, nxt;
+  const bool right = side != 0;
+  auto fetch = [&](int t, SiteOps& o) {
+    const int k = right ? n - 1 - t : t;
+    o.load(st + (size_t)k * SLOT, dim(k - 1), dim(k), right);
+  };
+  store_env(right ? n : 0);
+  fetch(0, cur);
+  for (int t = 0; t < n; ++t) {
+    if (t + 1 < n) fetch(t + 1, nxt);
+    cf eo[4];
+    acc_as_b(e, eo);
+    if (!right) {
+      // L_{k+1} = sum_u A_u^T L_k conj(A_u)
+      e = left_transfer_t<SPLIT>(eo, cur.a);
+    } else {
+      // R_k = sum_s A_s R_{k+1} A_s^H: Y_s = R A_s^H, R_k^T = sum_s Y_s^T A_s^T (row forms)
+      Acc o = acc_zero();
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        ld_rowop(at + s * 16 * TS, ah, true);   // B-operand of R A_s^H: conj(A_s[l%16][4g+kc])
+      for (int s_ = 0; s_ < 2; ++s_) {
+        cf ah[4], ya[4];
+        conj4(cur.a[s_], ah);
         Acc y = acc_zero();
-        cgemm<SPLIT>(y, r, ah);
-        acc_as_b(y, yb);
-        ld_rowop(at + s * 16 * TS, as_, false);  // A-operand A_s[l%16][4g+kc]
-        cgemm<SPLIT>(out, as_, yb);
+        cgemm<SPLIT>(y, eo, ah);
+        acc_as_b(y, ya);
+        cgemm<SPLIT>(o, ya, cur.a[s_]);
       }
-      __syncthreads();
-      st_acc(E, out);
-      __syncthreads();
-      store_env(k);
+      e = o;
     }
+    store_env(right ? n - 1 - t : t + 1);
+    cur = nxt;
   }
 }
 
@@ -266,20 +244,33 @@ __device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
   }
 }
 
+__device__ __forceinline__ cf cmul_f(cf a, cf b) { return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// Operands fetched one step ahead: the site (column form to carry through it and to open,
+// row form to close) and, at the open, L_i.  R_{j+1} and L_j are read at the close itself:
+// prefetching them too costs a register spill at three waves per SIMD, which is slower.
+struct PairStep {
+  SiteOps s;
+  cf li[4];
+};
+
 // One image and one start site i: st = its n slots, evL = its environments ([2][n+1][16][16]),
 // out = its [m][15] outputs.
+//  open at i:   X_s' = L_i conj(A_s'),  F^{0s'} = A_0^T X_s'   (s' = 0, 1)
+//  carry k:     F <- sum_u A_u^T F conj(A_u) for F^00 and F^01
+//  close at j:  Y_t' = R_{j+1} A_t'^H,  G^{tt'} = A_t Y_t',  F^11 = L_j - F^00
+//               rho[(s,t),(s',t')] = sum_{d,d'} F^{ss'}[d][d'] G^{tt'}[d][d']
+// F^{ss'} and G^{tt'} are held transposed (lane: entry (x, y) = (l%16, 4g+r)), G^01 also
+// untransposed (entry (y, x)), so every upper-triangle entry of the Hermitian rho is a sum of
+// lane-local products: only F^{ss'} with s <= s' appear there, and G^10[x][y] = conj(G^01[y][x]).
 template <bool SPLIT>
 __device__ __forceinline__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
                               int chi, int layers, int i, float* out) {
-  __shared__ cf F[3][16 * TS];
-  __shared__ cf at[2 * 16 * TS];
-  __shared__ cf Ev[16 * TS];
   __shared__ int tq[kMaxTargets16], tj[kMaxTargets16];
   __shared__ int cnt;
-  __shared__ float rho[32];
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  const int l = threadIdx.x, g = l >> 4, lj = l & 15;
+  const int l = threadIdx.x;
   const float* evR = evL + (size_t)(n + 1) * ETILE;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
   const float qnan = __builtin_nanf("");
@@ -302,7 +293,7 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
     }
   }
   __syncthreads();
-  const int nt = min(cnt, kMaxTargets16);
+  const int nt = uniform_int(min(cnt, kMaxTargets16));
   if (nt == 0) return;
   if (l == 0) {
     for (int x = 1; x < nt; ++x) {
@@ -317,170 +308,133 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
       tq[y + 1] = kq;
     }
   }
-  // Sites are visited in order i, i+1, ..., j_last; `at` holds the tile of site at_site and
-  // the registers of `pf` hold the next site, loaded while the current one is contracted.
-  const int jlast = tj[nt - 1];
-  SiteRegs pf;
-  int at_site = -1;
-  pf.load(st + (size_t)i * SLOT, dim(i - 1), dim(i));
-  auto need = [&](int s_) {
-    if (at_site == s_) return;
-    __syncthreads();
-    pf.commit(at);
-    at_site = s_;
-    if (s_ + 1 <= jlast) pf.load(st + (size_t)(s_ + 1) * SLOT, dim(s_), dim(s_ + 1));
-    __syncthreads();
-  };
-  env_to_lds(Ev, evL + (size_t)i * ETILE);
-  need(i);
-  // ---- open: X_s' = L conj(A_s'); F^{ss'} = A_s^T X_s'
-  {
-    cf lo[4], a0[4], a1[4], ac[4], x0[4], x1[4];
-    ld_rowop(Ev, lo, false);
-    ld_colop(at, a0, false);
-    ld_colop(at + 16 * TS, a1, false);
-    Acc x = acc_zero();
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{a0[kc].re, -a0[kc].im};
-    cgemm<SPLIT>(x, lo, ac);
-    acc_as_b(x, x0);
-    x = acc_zero();
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) ac[kc] = cf{a1[kc].re, -a1[kc].im};
-    cgemm<SPLIT>(x, lo, ac);
-    acc_as_b(x, x1);
-    Acc f00 = acc_zero(), f01 = acc_zero();
-    cgemm<SPLIT>(f00, a0, x0);
-    cgemm<SPLIT>(f01, a0, x1);
-    st_acc(F[0], f00);
-    st_acc(F[1], f01);
-  }
   __syncthreads();
-  int cur = i + 1;
-  for (int x = 0; x < nt; ++x) {
-    const int j = tj[x], q = tq[x];
-    // ---- propagate through sites cur .. j-1
-    for (; cur < j; ++cur) {
-      need(cur);
-      cf a0[4], a1[4], e[4];
-      ld_colop(at, a0, false);
-      ld_colop(at + 16 * TS, a1, false);
-      Acc nf[2];
-#pragma unroll
-      for (int blk = 0; blk < 2; ++blk) {
-        ld_rowop(F[blk], e, false);
-        nf[blk] = left_transfer<SPLIT>(e, a0, a1);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int blk = 0; blk < 2; ++blk) st_acc(F[blk], nf[blk]);
-      __syncthreads();
+
+  // Steps: 2 = open at i, 0 = carry through site `site`, 1 = close at the next target.
+  int x = 0, cur = i + 1;
+  auto successor = [&](int kind, int site, int& nk, int& ns) {
+    int xx = x, cc = cur;
+    if (kind == 1) ++xx;
+    else if (kind == 0) cc = site + 1;
+    if (xx >= nt) {
+      nk = -1;
+      ns = 0;
+      return;
     }
-    // ---- close at j: Y_t' = R A_t'^H ; G^{tt'} = A_t Y_t'
-    env_to_lds(Ev, evR + (size_t)(j + 1) * ETILE);
-    // F^{11} = L_j - F^{00}: the two diagonal blocks of the open index sum to the left
-    // environment of site j, so only F^{00} and F^{01} are carried through the sites between.
-    {
-      const float* lj = evL + (size_t)j * ETILE;
-      for (int idx = l; idx < 256; idx += W) {
-        const int r = idx >> 4, c = idx & 15;
-        const cf f0 = F[0][r * TS + c];
-        F[2][r * TS + c] = cf{lj[2 * idx] - f0.re, lj[2 * idx + 1] - f0.im};
-      }
-    }
-    need(j);
-    __syncthreads();
-    Acc G[3];
-    {
-      cf r[4], ah[4], y0[4], y1[4], as_[4];
-      ld_rowop(Ev, r, false);
-      ld_rowop(at, ah, true);
+    const int j = uniform_int(tj[xx]);
+    nk = cc < j ? 0 : 1;
+    ns = cc < j ? cc : j;
+  };
+  auto fetch = [&](int kind, int site, PairStep& p) {
+    p.s.load(st + (size_t)site * SLOT, dim(site - 1), dim(site), kind == 1);
+    if (kind == 2) ld_env_row(evL + (size_t)site * ETILE, p.li);
+  };
+  PairStep pa, pb;
+  int kind = 2, site = i;
+  fetch(kind, site, pa);
+  Acc F0 = acc_zero(), F1 = acc_zero();  // F^00, F^01, transposed
+  while (kind >= 0) {
+    int nk, ns;
+    successor(kind, site, nk, ns);
+    if (nk >= 0) fetch(nk, ns, pb);
+    if (kind == 2) {
+      cf ac[4], xa[4];
+      conj4(pa.s.a[0], ac);
+      Acc x0 = acc_zero();
+      cgemm<SPLIT>(x0, pa.li, ac);
+      acc_as_b(x0, xa);
+      F0 = acc_zero();
+      cgemm<SPLIT>(F0, xa, pa.s.a[0]);
+      conj4(pa.s.a[1], ac);
+      Acc x1 = acc_zero();
+      cgemm<SPLIT>(x1, pa.li, ac);
+      acc_as_b(x1, xa);
+      F1 = acc_zero();
+      cgemm<SPLIT>(F1, xa, pa.s.a[0]);
+    } else if (kind == 0) {
+      cf fo[4];
+      acc_as_b(F0, fo);
+      const Acc n0 = left_transfer_t<SPLIT>(fo, pa.s.a);
+      acc_as_b(F1, fo);
+      F1 = left_transfer_t<SPLIT>(fo, pa.s.a);
+      F0 = n0;
+    } else {
+      cf rj[4], lj[4];
+      ld_env_row(evR + (size_t)(site + 1) * ETILE, rj);
+      ld_env_row(evL + (size_t)site * ETILE, lj);
+      // Y_t' = R A_t'^H (B-operand conj of the row form); G^{tt'T} = Y_t'^T A_t^T; G^01 = A_0 Y_1
+      cf ah[4], y0a[4], y1a[4];
+      conj4(pa.s.a[0], ah);
       Acc y = acc_zero();
-      cgemm<SPLIT>(y, r, ah);
-      acc_as_b(y, y0);
-      ld_rowop(at + 16 * TS, ah, true);
+      cgemm<SPLIT>(y, rj, ah);
+      acc_as_b(y, y0a);
+      conj4(pa.s.a[1], ah);
       y = acc_zero();
-      cgemm<SPLIT>(y, r, ah);
-      acc_as_b(y, y1);
-      G[0] = acc_zero();
-      G[1] = acc_zero();
-      G[2] = acc_zero();
-      ld_rowop(at, as_, false);
-      cgemm<SPLIT>(G[0], as_, y0);
-      cgemm<SPLIT>(G[1], as_, y1);
-      ld_rowop(at + 16 * TS, as_, false);
-      cgemm<SPLIT>(G[2], as_, y1);
-    }
-    // rho[(s,t),(s',t')] = sum_{d,d'} F^{ss'}[d][d'] G^{tt'}[d][d'];  entry e = ((s*2+t)*2+s')*2+t'
-    float part[32];
+      cgemm<SPLIT>(y, rj, ah);
+      acc_as_b(y, y1a);
+      Acc g00 = acc_zero(), g01 = acc_zero(), g11 = acc_zero(), h01 = acc_zero();
+      cgemm<SPLIT>(g00, y0a, pa.s.a[0]);
+      cgemm<SPLIT>(g01, y1a, pa.s.a[0]);
+      cgemm<SPLIT>(g11, y1a, pa.s.a[1]);
+      cgemm<SPLIT>(h01, pa.s.a[0], y1a);
+      // upper triangle of rho, entry (row, col) with row = s*2+t, col = s'*2+t'
+      float d00 = 0.f, d11 = 0.f, d22 = 0.f, d33 = 0.f;
+      cf e01{0.f, 0.f}, e02{0.f, 0.f}, e03{0.f, 0.f}, e12{0.f, 0.f}, e13{0.f, 0.f}, e23{0.f, 0.f};
 #pragma unroll
-    for (int e = 0; e < 32; ++e) part[e] = 0.f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int d = 4 * g + r, dp = lj;
-      // F blocks at (d, dp) and at (dp, d)
-      cf fa[3], fb[3];
-#pragma unroll
-      for (int blk = 0; blk < 3; ++blk) {
-        fa[blk] = F[blk][d * TS + dp];
-        fb[blk] = F[blk][dp * TS + d];
+      for (int r = 0; r < 4; ++r) {
+        const cf f00{F0.re[r], F0.im[r]}, f01{F1.re[r], F1.im[r]};
+        const cf f11{lj[r].re - f00.re, lj[r].im - f00.im};
+        const cf G00{g00.re[r], g00.im[r]}, G01{g01.re[r], g01.im[r]}, G11{g11.re[r], g11.im[r]};
+        const cf G10{h01.re[r], -h01.im[r]};
+        d00 += f00.re * G00.re - f00.im * G00.im;
+        d11 += f00.re * G11.re - f00.im * G11.im;
+        d22 += f11.re * G00.re - f11.im * G00.im;
+        d33 += f11.re * G11.re - f11.im * G11.im;
+        const cf p01 = cmul_f(f00, G01), p02 = cmul_f(f01, G00), p03 = cmul_f(f01, G01);
+        const cf p12 = cmul_f(f01, G10), p13 = cmul_f(f01, G11), p23 = cmul_f(f11, G01);
+        e01 = cf{e01.re + p01.re, e01.im + p01.im};
+        e02 = cf{e02.re + p02.re, e02.im + p02.im};
+        e03 = cf{e03.re + p03.re, e03.im + p03.im};
+        e12 = cf{e12.re + p12.re, e12.im + p12.im};
+        e13 = cf{e13.re + p13.re, e13.im + p13.im};
+        e23 = cf{e23.re + p23.re, e23.im + p23.im};
       }
-      const cf g00{G[0].re[r], G[0].im[r]}, g01{G[1].re[r], G[1].im[r]}, g11{G[2].re[r], G[2].im[r]};
+      d00 = wave_sum_f(d00);
+      d11 = wave_sum_f(d11);
+      d22 = wave_sum_f(d22);
+      d33 = wave_sum_f(d33);
+      e01 = cf{wave_sum_f(e01.re), wave_sum_f(e01.im)};
+      e02 = cf{wave_sum_f(e02.re), wave_sum_f(e02.im)};
+      e03 = cf{wave_sum_f(e03.re), wave_sum_f(e03.im)};
+      e12 = cf{wave_sum_f(e12.re), wave_sum_f(e12.im)};
+      e13 = cf{wave_sum_f(e13.re), wave_sum_f(e13.im)};
+      e23 = cf{wave_sum_f(e23.re), wave_sum_f(e23.im)};
+      // full rho (row-major 4x4): lower triangle = conjugate transpose
+      const cf rho[16] = {cf{d00, 0.f}, e01, e02, e03,
+                          cf{e01.re, -e01.im}, cf{d11, 0.f}, e12, e13,
+                          cf{e02.re, -e02.im}, cf{e12.re, -e12.im}, cf{d22, 0.f}, e23,
+                          cf{e03.re, -e03.im}, cf{e13.re, -e13.im}, cf{e23.re, -e23.im}, cf{d33, 0.f}};
+      if (l < 15) {
+        // <P_a (x) P_c> = sum_{s,t,s',t'} rho[(s,t),(s',t')] P_a[s'][s] P_c[t'][t]
+        const int al = l + 1, pa_ = al >> 2, pc = al & 3;
+        float acc = 0.f;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
-        // G^{tt'} at (d,dp); for (t,t')=(1,0) use conj(G01) paired with the transposed position.
-        const bool gt = (t == 1 && tp == 0);
-        const cf gv = gt ? cf{g01.re, -g01.im} : (t + tp == 0 ? g00 : (t + tp == 1 ? g01 : g11));
-        // F^{ss'} at (d,dp) [or at (dp,d) when G was transposed]
-        cf fv;
-        if (s == 1 && sp == 0) {
-          // F^{10}[x][y] = conj(F01[y][x])
-          const cf src = gt ? fa[1] : fb[1];
-          fv = cf{src.re, -src.im};
-        } else {
-          fv = gt ? fb[s + sp] : fa[s + sp];
+        for (int e = 0; e < 16; ++e) {
+          const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
+          const float ar = pauli_re(pa_, sp, s, false), ai = pauli_re(pa_, sp, s, true);
+          const float cr = pauli_re(pc, tp, t, false), ci = pauli_re(pc, tp, t, true);
+          const float wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
+          const cf rv = rho[(s * 2 + t) * 4 + sp * 2 + tp];
+          acc += rv.re * wr - rv.im * wi;
         }
-        // rho is Hermitian (row (s,t) = e >> 2, column (s',t') = e & 3): only the upper
-        // triangle is accumulated, and only the real part on the diagonal.
-        if ((e >> 2) <= (e & 3)) {
-          part[2 * e] += fv.re * gv.re - fv.im * gv.im;
-          if ((e >> 2) < (e & 3)) part[2 * e + 1] += fv.re * gv.im + fv.im * gv.re;
-        }
+        out[(size_t)uniform_int(tq[x]) * 15 + l] = acc;
       }
     }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      if ((e >> 2) <= (e & 3)) part[2 * e] = wave_sum_f(part[2 * e]);
-      if ((e >> 2) < (e & 3)) part[2 * e + 1] = wave_sum_f(part[2 * e + 1]);
-    }
-    if (l < 32) {
-      // entry e = l/2; a lower-triangle entry is the conjugate of its transpose e' = col*4 + row
-      const int e = l >> 1, row = e >> 2, col = e & 3;
-      const int src = row <= col ? e : col * 4 + row;
-      const bool im = l & 1;
-      float v = 0.f;
-#pragma unroll
-      for (int x = 0; x < 32; ++x) v = (x == 2 * src + (im ? 1 : 0)) ? part[x] : v;
-      if (im && row > col) v = -v;
-      if (im && row == col) v = 0.f;
-      rho[l] = v;
-    }
-    __syncthreads();
-    if (l < 15) {
-      const int al = l + 1, pa = al >> 2, pc = al & 3;
-      float acc = 0.f;
-      for (int e = 0; e < 16; ++e) {
-        const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
-        // w = P_a[s'][s] * P_c[t'][t]
-        const float ar = pauli_re(pa, sp, s, false), ai = pauli_re(pa, sp, s, true);
-        const float cr = pauli_re(pc, tp, t, false), ci = pauli_re(pc, tp, t, true);
-        const float wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
-        acc += rho[2 * e] * wr - rho[2 * e + 1] * wi;
-      }
-      out[(size_t)q * 15 + l] = acc;
-    }
-    __syncthreads();
+    if (kind == 1) ++x;
+    else if (kind == 0) cur = site + 1;
+    kind = nk;
+    site = ns;
+    pa = pb;
   }
 }
 
@@ -498,8 +452,8 @@ __global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int
               layers, side);
 }
 
-// Three waves per SIMD instead of the two its 246 registers allow: the compiler spills ~100
-// bytes per lane, and the launch is ~4 % faster with the extra wave hiding MFMA and LDS latency.
+// Three waves per SIMD (168 registers, no spill): measured faster than two or four, the extra
+// wave hiding MFMA and load latency.
 template <bool SPLIT>
 __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pairs16(const float* state, const float* env,
                                                 const int* pairs, int m, int n, int chi,
