@@ -33,15 +33,14 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0,
 # the factors a 1 GiB device copy reads), valid only for the kernel source they were taken on.
 MEASURED_TRAFFIC = {
-    # one layer call, averaged over the four layers of the workload: k_mpo_ends + k_mpo_sites
-    "layer": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-              "sha1": "8cc5138f1c1a9de973cf5a1252871156e4445f6b",
-              "bytes": ((2 * 42037.1 + 167936.0) + (2 * 22068.5 + 44032.0) + (2 * 11572.5 + 11520.0)
-                        + (2 * 6068.5 + 6016.0) + 4 * (2 * 2175.6 + 2016.0)) / 4 * 1024},
+    # one mps_apply_layers call (all four layers): k_mpo_run_core + k_mpo_run_ends
+    "layers": {"source": "paper_2607_10280_amd/csrc/layer.hip",
+               "sha1": "28194a05ecea28bdecd15c0f2f0392dc7972ce8a",
+               "bytes": ((2 * 5319.4 + 167936.0) + (2 * 5053.2 + 6118.7)) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
                 "sha1": "ea0c34a60e032bda24de21e4cd0d4a1dbacc1bde",
-                "bytes": (2 * (194884.7 + 234909.5) + (204807.8 + 5897.5)) * 1024},
+                "bytes": (2 * (194891.9 + 236586.9) + (204801.2 + 5904.2)) * 1024},
 }
 
 
@@ -191,7 +190,8 @@ def run_mixed(args):
     t = time.perf_counter()
     for i in sample:
         sp = specs[i]
-        o, _ = anomps.extract_features(sp.pixels[None], sp.theta, sp.phi, sp.pairs, sp.chi, prec)
+        o, _ = anomps.extract_features(sp.pixels[None], sp.theta, sp.phi, sp.pairs, sp.chi, prec,
+                                       per_layer=True)
         same += int(np.array_equal(o.cpu().numpy()[0], outs[i]))
     plain_s = (time.perf_counter() - t) / len(sample)
     small = [i for i in sample if specs[i].n <= 64][:4]
@@ -273,7 +273,7 @@ def run_serve(args):
     serving.Server(1 << 30).run(check)
     same = sum(int(np.array_equal(r.features, anomps.extract_features(
         r.spec.pixels[None], r.spec.theta, r.spec.phi, r.spec.pairs, r.spec.chi,
-        prec)[0].cpu().numpy()[0])) for r in check)
+        prec, per_layer=True)[0].cpu().numpy()[0])) for r in check)
     result = {
         "metric": "serving p50/p99 latency and throughput (Poisson arrivals, mixed p/L/chi)",
         "value": runs["0.9x"]["latency_ms_p99"], "unit": "ms (p99 at 0.9x saturation)",
@@ -517,9 +517,8 @@ def main():
         mark("start")
         anomps.init_batch(b, pix)
         mark("encode")
-        for layer in range(L):
-            anomps.apply_layer(b, th_d[layer], ph_d[layer])
-            mark("layer")
+        anomps.apply_layers(b, th_d, ph_d)
+        mark("layers")
         anomps.pauli_pair_expect(b, pairs_d, out)
         mark("measure")
         anomps.ano_coeffs(A_d, B_d, D_d, coeff_d)
@@ -559,8 +558,8 @@ def main():
         torch.cuda.synchronize()
         for (_, a), (name, b) in zip(evs[:-1], evs[1:]):
             per.setdefault(name, []).append(a.elapsed_time(b))
-    avg = {k: float(np.mean(v)) for k, v in per.items()}   # ms per call (layer: per layer call)
-    per_step = {"encode": avg["encode"], "layers": avg["layer"] * L, "measure": avg["measure"],
+    avg = {k: float(np.mean(v)) for k, v in per.items()}   # ms per call
+    per_step = {"encode": avg["encode"], "layers": avg["layers"], "measure": avg["measure"],
                 "readout": avg["readout"]}
 
     # Plain method: one image per call, serial, on the same GPU.
@@ -606,16 +605,16 @@ def main():
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
     mfma = prec == anomps.PREC_FP32 and anomps.slot_dim(n, chi, L) == 16
     cand = {
-        "layer": (lay_flops / L, avg["layer"], "alu", PEAK_FP64_TFLOPS,
-                  "FP64 VALU, per layer call: gates + parity-operator contraction with exact "
-                  "end carries for layers that keep every singular value, else Jacobi SVD "
-                  "(nominal R-SVD count) + canonical sweep"),
+        "layers": (lay_flops, avg["layers"], "alu", PEAK_FP64_TFLOPS,
+                   "FP64 VALU, per mps_apply_layers call (all L layers): gates + parity-operator "
+                   "contraction with exact end carries for layers that keep every singular "
+                   "value, else Jacobi SVD (nominal R-SVD count) + canonical sweep"),
         "measure": (meas_flops, avg["measure"], "mfma" if mfma else "alu",
                     PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else
                     (PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS),
                     "environments + pair contractions, per measurement call"),
     }
-    dom = max(cand, key=lambda k: per_step["layers" if k == "layer" else k])
+    dom = max(cand, key=lambda k: per_step[k])
     fl, dur_ms, bound, peak, what = cand[dom]
     achieved = fl / (dur_ms * 1e-3) / 1e12
     traffic = _measured_traffic(dom)
@@ -624,9 +623,9 @@ def main():
                 "traffic": None if traffic is None else round(traffic),
                 "kernel": dom, "what": what, "flops_per_launch": fl,
                 "avg_launch_ms": round(dur_ms, 4)}
-    if dom == "layer":
+    if dom == "layers":
         alg = sum(workload.layer_bytes(n, chi, l, 8 if prec == anomps.PREC_FP64 else 4)
-                  for l in range(L)) / L * B
+                  for l in range(L)) * B
         roofline["algorithmic_bytes_per_launch"] = round(alg)
 
     result = {

@@ -148,6 +148,23 @@ int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double
                     hipStream_t stream);
 
 /*
+ * Apply the next `count` ladder layers (§II-B) in one call: the same result as `count` calls of
+ * mps_apply_layer with theta + r*n_sites, phi + r*n_sites and trunc_err + r*batch*(n_sites-1),
+ * r = 0..count-1.  Under MPS_EXACT_MPO (slots <= 16) a run of two or more consecutive layers that
+ * keep every singular value is applied by two launches: the sites that lie between the reduced
+ * chain ends in every layer of the run take all of the run's layers in on-chip memory and are
+ * written once; the ends take the layers one after the other.  The state is the one the
+ * separate calls produce up to rounding: in complex64 the run's intermediate tensors stay in
+ * FP64 instead of being rounded to FP32 after each layer.
+ *  theta, phi : device [count][n_sites] float64.
+ *  trunc_err  : device [count][batch][n_sites-1] float64 or NULL.
+ * Errors: MPS_ERR_INVALID_ARG if count < 1 or layers_done + count > n_layers, and as
+ *   mps_apply_layer.
+ */
+int mps_apply_layers(mps_batch* b, int32_t count, const double* theta, const double* phi,
+                     double* trunc_err, hipStream_t stream);
+
+/*
  * How mps_apply_layer (and the mixed layer step) handle a layer in which the bond rule keeps
  * every singular value, i.e. D_k = min(2 D_{k-1}, 2 D_{k+1}^old) at every bond k (always the
  * case when chi >= 2^n_layers, the exact regime of §II-B).  Nothing can be discarded in such a

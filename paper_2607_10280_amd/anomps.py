@@ -87,6 +87,8 @@ EXPORTS = {
     "mps_init_batch": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p]),
     "mps_apply_layer": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_apply_layers": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mps_apply_layer_program": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_int32,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
@@ -216,6 +218,16 @@ def apply_layer(b: Batch, theta, phi, trunc_err=None, stream=None) -> None:
                                  _stream(stream)))
 
 
+def apply_layers(b: Batch, theta, phi, trunc_err=None, stream=None) -> None:
+    """The next theta.shape[0] ladder layers in one call; theta, phi: device [count][n_sites]
+    float64, trunc_err: device [count][batch][n_sites-1] float64 or None."""
+    for t in (theta, phi):
+        assert t.is_cuda and t.is_contiguous() and t.dim() == 2 and t.shape[1] == b.desc.n_sites
+    assert theta.shape == phi.shape
+    _check(lib().mps_apply_layers(ctypes.byref(b.desc), int(theta.shape[0]), _ptr(theta), _ptr(phi),
+                                  _ptr(trunc_err), _stream(stream)))
+
+
 def apply_layer_program(b: Batch, program: int, theta=None, phi=None, pixels=None,
                         trunc_err=None, stream=None) -> None:
     _check(lib().mps_apply_layer_program(ctypes.byref(b.desc), program, _ptr(theta), _ptr(phi),
@@ -279,8 +291,9 @@ class AnoTrainer:
 
 
 def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_FP32,
-                     stream=None, return_trunc_err: bool = False):
-    """Whole path for one batch: encode, all layers, Pauli-pair expectations.
+                     stream=None, return_trunc_err: bool = False, per_layer: bool = False):
+    """Whole path for one batch: encode, all layers (one mps_apply_layers call, or one
+    mps_apply_layer call per layer with per_layer=True), Pauli-pair expectations.
 
     pixels [B][n] (host numpy or device tensor), theta/phi [L][n], pairs [m][2] (numpy, validated
     on the host).  Returns device tensors (features [B][m][15], status [B][, trunc_err [B][L][n-1]]).
@@ -297,11 +310,17 @@ def extract_features(pixels, theta, phi, pairs, chi: int, precision: int = PREC_
     b = new_batch(n, chi, L, B, precision)
     init_batch(b, pix, stream)
     te = torch.zeros((B, max(L, 1), n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
-    for layer in range(L):
-        tl = torch.empty((B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
-        apply_layer(b, th[layer], ph[layer], tl, stream)
+    if per_layer:
+        for layer in range(L):
+            tl = torch.empty((B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+            apply_layer(b, th[layer], ph[layer], tl, stream)
+            if return_trunc_err:
+                te[:, layer] = tl
+    elif L > 0:
+        tl = torch.empty((L, B, n - 1), dtype=torch.float64, device=dev) if return_trunc_err else None
+        apply_layers(b, th, ph, tl, stream)
         if return_trunc_err:
-            te[:, layer] = tl
+            te[:, :L] = tl.permute(1, 0, 2)
     pd = torch.as_tensor(pairs_np, device=dev)
     out = torch.empty((B, len(pairs_np), 15), dtype=b.real_dtype, device=dev)
     pauli_pair_expect(b, pd, out, stream)

@@ -212,6 +212,38 @@ int mps_apply_layer(mps_batch* b, const double* theta, const double* phi, double
   return mps_apply_layer_program(b, MPS_LAYER_RYRZ_LADDER, theta, phi, nullptr, trunc_err, stream);
 }
 
+int mps_apply_layers(mps_batch* b, int32_t count, const double* theta, const double* phi,
+                     double* trunc_err, hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!theta || !phi) return fail(MPS_ERR_INVALID_ARG, "theta/phi is NULL");
+  if (count < 1) return fail(MPS_ERR_INVALID_ARG, "count=%d < 1", count);
+  if (b->layers_done < 0 || b->layers_done + count > b->n_layers)
+    return fail(MPS_ERR_INVALID_ARG, "layers_done=%d + count=%d: batch sized for %d layers",
+                b->layers_done, count, b->n_layers);
+  const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
+  if (S > kMaxBond) {
+    // wide slots: one layer call after the other
+    const size_t n = (size_t)b->n_sites, te = (size_t)b->batch * (n - 1);
+    for (int r = 0; r < count; ++r) {
+      rc = mps_apply_layer(b, theta + r * n, phi + r * n, trunc_err ? trunc_err + r * te : nullptr,
+                           stream);
+      if (rc) return rc;
+    }
+    return ok();
+  }
+  hipError_t e;
+  if (b->precision == MPS_PREC_FP64)
+    e = launch_layers<double>((double*)b->state, b->n_sites, b->chi, S, b->layers_done, count,
+                              b->batch, theta, phi, trunc_err, b->status, stream);
+  else
+    e = launch_layers<float>((float*)b->state, b->n_sites, b->chi, S, b->layers_done, count,
+                             b->batch, theta, phi, trunc_err, b->status, stream);
+  if (e != hipSuccess) return check_hip(e, "layer launch");
+  b->layers_done += count;
+  return ok();
+}
+
 int mps_init_zero(mps_batch* b, hipStream_t stream) {
   int rc = check_batch(b);
   if (rc) return rc;

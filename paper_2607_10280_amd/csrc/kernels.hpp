@@ -13,6 +13,11 @@ hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch
 
 // program 0: R_Y R_Z gates + CNOT ladder (theta, phi); program 1: the paper's H, R_Y(2 pi x - pi)
 // gates from pixels + brickwork CNOTs.
+// `count` ladder layers from `layer` (theta, phi [count][n]; trunc_err [count][batch][n-1]).
+template <typename T>
+hipError_t launch_layers(T* state, int n, int chi, int S, int layer, int count, int batch,
+                         const double* theta, const double* phi, double* trunc_err, int* status,
+                         hipStream_t stream);
 template <typename T>
 hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, int program,
                         const double* theta, const double* phi, const double* pixels,

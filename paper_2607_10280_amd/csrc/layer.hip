@@ -5,6 +5,9 @@
 // independent, so a batch fills the machine with one wavefront per image.  Site tensors live
 // in HBM in the slot layout [site][S][2][S] (storage type T: double or float); the tensors of
 // the current bond are staged in LDS in FP64 and every factorisation runs in FP64.
+#include <algorithm>
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -998,8 +1001,23 @@ __device__ __forceinline__ bool mpo_plain_site(const At& at, const Gate2& g, int
 //  part 2: both ends.
 // The next site's load overlaps each carry step, and the identity tensors are stored after the
 // last load, so that no step waits for earlier stores.  Returns true if a value is not finite.
+// LDS of the end carries: left carry ping-pong c[2] (S x 2S each, the free one also holds the
+// carry site's product), right carry ping-pong r[2] (2S x S each), the staged old tensor tb.
+// A part that does not take an end may leave its two pointers null.
+template <typename T>
+struct MpoBufs {
+  cd* c[2];
+  cd* r[2];
+  cx<T>* tb;
+};
+
+template <int S, typename T>
+__device__ __forceinline__ MpoBufs<T> mpo_bufs(LayerShared<S, T>& sh) {
+  return MpoBufs<T>{{sh.mat, sh.mat + S * 2 * S}, {sh.uq, sh.ta}, sh.tb};
+}
+
 template <int S, typename T, typename Before, typename After>
-__device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After dnew,
+__device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, After dnew,
                          const MpoPlan& plan, const double* theta, const double* phi,
                          SitePrefetch<S, T>& pf, int part) {
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
@@ -1011,7 +1029,8 @@ __device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After
   const bool do_left = part != 1, do_right = part != 0 || meet;
   // MPO bond size on the left of site k: 2 D_{k-1}^old (1 at site 0).
   auto lm = [&](int k) { return k == 0 ? 1 : 2 * dold(k - 1); };
-  auto at = [&](int a, int s_, int b) { return to_cd(sh.tb[(a * 2 + s_) * SP + b]); };
+  cx<T>* tb = bufs.tb;
+  auto at = [&](int a, int s_, int b) { return to_cd(tb[(a * 2 + s_) * SP + b]); };
   // Visiting order: left chain 0..kl, right chain n-1..kr+1, then the carry sites.
   const int nl = do_left ? kl + 1 : 0, nr = do_right ? n - 1 - kr : 0;
   const bool two = do_left && do_right && !meet;
@@ -1021,32 +1040,39 @@ __device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After
     if (t < nl + nr) return n - 1 - (t - nl);
     return (t == nl + nr && do_left) ? kl + 1 : kr;
   };
-  cd* cbuf[2] = {sh.mat, sh.mat + S * CS};
-  cd* rbuf[2] = {sh.uq, sh.ta};
+  cd* const c0 = bufs.c[0];
+  cd* const c1 = bufs.c[1];
+  cd* const r0 = bufs.r[0];
+  cd* const r1 = bufs.r[1];
+  auto cbuf = [&](int i) { return i ? c1 : c0; };
+  auto rbuf = [&](int i) { return i ? r1 : r0; };
   int cur = 0, rcur = 0;
   if (tid == 0) {
-    cbuf[0][0] = cd{1.0, 0.0};
-    rbuf[0][0] = cd{1.0, 0.0};
+    if (do_left) c0[0] = cd{1.0, 0.0};
+    if (do_right) r0[0] = cd{1.0, 0.0};
   }
   bool bad = false;
   pf.load(st + (size_t)site_at(0) * SLOT, dold(site_at(0) - 1), dold(site_at(0)));
+  Gate2 gnext = site_gate(kGateRyRz, site_at(0), theta, phi, nullptr);
   for (int t = 0; t < total; ++t) {
     const int k = site_at(t);
-    pf.commit(sh.tb);
+    pf.commit(tb);
     __syncthreads();
+    const Gate2 g = gnext;
     if (t + 1 < total) {
+      // the next site's load and gate overlap this step
       const int kn = site_at(t + 1);
       pf.load(st + (size_t)kn * SLOT, dold(kn - 1), dold(kn));
+      gnext = site_gate(kGateRyRz, kn, theta, phi, nullptr);
     }
-    const Gate2 g = site_gate(kGateRyRz, k, theta, phi, nullptr);
     const int Dp = dold(k - 1), Do = dold(k), L = lm(k);
     const FastDiv fdp(Dp), fdo(Do);
     if (t < nl) {
       // C_k[2a+s][(q,b)] = delta(q,s) sum_i C_{k-1}[a][i] B[k][i, s, (s,b)]
       const int rows = dnew(k - 1), R = 2 * Do;
       const FastDiv fr(R);
-      const cd* C = cbuf[cur];
-      cd* Cn = cbuf[cur ^ 1];
+      const cd* C = cbuf(cur);
+      cd* Cn = cbuf(cur ^ 1);
       for (int idx = tid; idx < rows * 2 * R; idx += kLayerThreads) {
         const int row = fr.q(idx), m = fr.r(idx), a = row >> 1, s_ = row & 1;
         const int q = fdo.q(m), b = fdo.r(m);
@@ -1060,8 +1086,8 @@ __device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After
       // R_k[i][s D_k + b] = sum_b' B[k][i, s, (s,b')] R_{k+1}[(s,b')][b]
       const int Dn = dnew(k), cols = 2 * Dn;
       const FastDiv fc(cols), fdn(Dn);
-      const cd* Rk = rbuf[rcur];
-      cd* Rn = rbuf[rcur ^ 1];
+      const cd* Rk = rbuf(rcur);
+      cd* Rn = rbuf(rcur ^ 1);
       for (int idx = tid; idx < L * cols; idx += kLayerThreads) {
         const int i = fc.q(idx), f = fc.r(idx), s_ = fdn.q(f), b = fdn.r(f);
         const int p = fdp.q(i), a = fdp.r(i);
@@ -1076,9 +1102,9 @@ __device__ bool mpo_ends(LayerShared<S, T>& sh, T* st, int n, Before dold, After
     } else {
       // a carry site: C B[k] when k = kl+1 (left end), B[k] R when k = kr (right end)
       const bool lc = do_left && k == kl + 1, rc = do_right && k == kr;
-      const cd* C = cbuf[cur];
-      const cd* Rc = rbuf[rcur];
-      cd* V = sh.mat + (cur ^ 1) * S * CS;  // free half of mat: [D_kl][2][D_k^old]
+      const cd* C = cbuf(cur);
+      const cd* Rc = rbuf(rcur);
+      cd* V = cbuf(cur ^ 1);  // the free left-carry buffer: [D_kl][2][D_k^old]
       const int rows = lc ? dnew(kl) : L;
       if (lc) {
         // V[a'][y][b'] = sum_i C[a'][i] (U A)[a(i), y XOR p(i), b']
@@ -1153,7 +1179,7 @@ __device__ int mpo_layer(LayerShared<S, T>& sh, T* st, int n, Before dold, After
   const int tid = threadIdx.x;
   if (trunc_err)
     for (int k = tid; k < n - 1; k += kLayerThreads) trunc_err[k] = 0.0;
-  bool bad = mpo_ends<S, T>(sh, st, n, dold, dnew, plan, theta, phi, pf, 2);
+  bool bad = mpo_ends<S, T>(mpo_bufs(sh), st, n, dold, dnew, plan, theta, phi, pf, 2);
   auto at = [&](int a, int s_, int b) { return to_cd(sh.tb[(a * 2 + s_) * SP + b]); };
   const int k0 = plan.kl + 2, k1 = plan.kr - 1;
   if (k0 <= k1) pf.load(st + (size_t)k0 * SLOT, dold(k0 - 1), dold(k0));
@@ -1177,7 +1203,10 @@ __device__ int mpo_layer(LayerShared<S, T>& sh, T* st, int n, Before dold, After
 //    at the new dimensions and the odd ones at the old.
 enum : int { kLayerRyRzLadder = 0, kLayerHRyBrickwork = 1 };
 
-template <int S, typename T>
+// WITH_MPO: the one-wavefront form of a layer applied as the parity product operator.  The
+// batched kernel leaves it out (the host sends such layers to k_mpo_ends / k_mpo_sites), which
+// keeps its register allocation that of the SVD and QR paths.
+template <int S, typename T, bool WITH_MPO>
 __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
                                             int program, const double* theta, const double* phi,
                                             const double* pix, double* trunc_err, int* status,
@@ -1194,7 +1223,7 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf, exact_qr);
   } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
     MpoPlan plan;
-    if (exact_qr == kExactMpo && mpo_plan(n, dold, dnew, plan))
+    if (WITH_MPO && exact_qr == kExactMpo && mpo_plan(n, dold, dnew, plan))
       flags |= mpo_layer<S, T>(sh, st, n, dold, dnew, plan, theta, phi, trunc_err, pf);
     else
       flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
@@ -1214,7 +1243,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
   __shared__ LayerShared<S, T> sh;
   const int b = blockIdx.x;
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
-  layer_chain<S, T>(sh, st, n, chi, layer, PROG, theta, phi,
+  layer_chain<S, T, false>(sh, st, n, chi, layer, PROG, theta, phi,
                     pixels ? pixels + (size_t)b * n : nullptr,
                     trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b, exact_qr);
 }
@@ -1236,7 +1265,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_ends(T* state, int n, int
   if (part == 0 && trunc_err)
     for (int k = threadIdx.x; k < n - 1; k += kLayerThreads) trunc_err[(size_t)b * (n - 1) + k] = 0.0;
   SitePrefetch<S, T> pf;
-  const bool bad = mpo_ends<S, T>(sh, state + (size_t)b * n * ((size_t)2 * S * S * 2), n, dold,
+  const bool bad = mpo_ends<S, T>(mpo_bufs(sh), state + (size_t)b * n * ((size_t)2 * S * S * 2), n, dold,
                                   dnew, plan, theta, phi, pf, part);
   if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
 }
@@ -1328,7 +1357,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request
     const double* theta = uniform_ptr(r->theta) + (size_t)layer * n;
     const double* phi = uniform_ptr(r->phi) + (size_t)layer * n;
     double* te = uniform_ptr(r->trunc_err);
-    layer_chain<S, T>(sh, uniform_ptr((T*)r->state), n, chi, layer, kLayerRyRzLadder, theta, phi,
+    layer_chain<S, T, true>(sh, uniform_ptr((T*)r->state), n, chi, layer, kLayerRyRzLadder, theta, phi,
                       nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1, exact_qr);
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = layer + 1;
@@ -1455,12 +1484,255 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- several exact layers per call
+// A run of consecutive layers that all keep every singular value.  The sites between the
+// reduced ends in every layer of the run (core_lo..core_hi) are local to the whole run: each
+// takes all of its layers in LDS (FP64) and is written once.  The ends take the layers one
+// after the other, each layer's ends plus the sites of that layer between its ends and the core.
+constexpr int kMaxRun = 16;
+
+struct MpoRun {
+  int layer0, count, core_lo, core_hi;
+  MpoPlan plan[kMaxRun];
+};
+
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_mpo_run_ends(T* state, int n, int chi, MpoRun run,
+                                                                const double* theta,
+                                                                const double* phi,
+                                                                double* trunc_err, int* status,
+                                                                int batch) {
+  // One end per workgroup (a run never has the two carries meeting in one site), so the carry
+  // LDS holds one ping-pong pair: ~21 KiB at S = 16 instead of the layer kernel's ~39 KiB.
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  constexpr int SP = LayerShared<S, T>::SP;
+  __shared__ cd pool[2 * 2 * S * S];
+  __shared__ cx<T> tbuf[2 * S * SP];
+  const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
+  const int b = kXcds * (j >> 1) + xcd, part = j & 1;
+  if (b >= batch) return;
+  const int tid = threadIdx.x;
+  T* st = state + (size_t)b * n * SLOT;
+  SitePrefetch<S, T> pf;
+  const MpoBufs<T> bufs =
+      part == 0 ? MpoBufs<T>{{pool, pool + 2 * S * S}, {nullptr, nullptr}, tbuf}
+                : MpoBufs<T>{{nullptr, nullptr}, {pool, pool + 2 * S * S}, tbuf};
+  auto at = [&](int a, int s_, int c) { return to_cd(tbuf[(a * 2 + s_) * SP + c]); };
+  bool bad = false;
+  for (int r = 0; r < run.count; ++r) {
+    const int layer = run.layer0 + r;
+    auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
+    auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
+    const double* th = theta + (size_t)r * n;
+    const double* ph = phi + (size_t)r * n;
+    if (part == 0 && trunc_err)
+      for (int k = tid; k < n - 1; k += kLayerThreads)
+        trunc_err[((size_t)r * batch + b) * (n - 1) + k] = 0.0;
+    const MpoPlan plan = run.plan[r];
+    bad |= mpo_ends<S, T>(bufs, st, n, dold, dnew, plan, th, ph, pf, part);
+    // this layer's sites between its own ends and the core, on this side
+    const int k0 = part == 0 ? plan.kl + 2 : run.core_hi + 1;
+    const int k1 = part == 0 ? run.core_lo - 1 : plan.kr - 1;
+    Gate2 gnext{};
+    if (k0 <= k1) {
+      pf.load(st + (size_t)k0 * SLOT, dold(k0 - 1), dold(k0));
+      gnext = site_gate(kGateRyRz, k0, th, ph, nullptr);
+    }
+    for (int k = k0; k <= k1; ++k) {
+      pf.commit(tbuf);
+      __syncthreads();
+      const Gate2 g = gnext;
+      if (k + 1 <= k1) {
+        pf.load(st + (size_t)(k + 1) * SLOT, dold(k), dold(k + 1));
+        gnext = site_gate(kGateRyRz, k + 1, th, ph, nullptr);
+      }
+      bad |= mpo_plain_site<S, T>(at, g, dold(k - 1), dold(k), st + (size_t)k * SLOT, tid,
+                                  kLayerThreads);
+      __syncthreads();
+    }
+    // the next layer reads what this one stored: the barrier's fence makes it visible
+    __syncthreads();
+  }
+  if (__any(bad) && tid == 0) atomicOr(status + b, kImgNonfinite);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_mpo_run_core(T* state, int n, int chi, MpoRun run,
+                                                                const double* theta,
+                                                                const double* phi, int* status,
+                                                                int batch) {
+  // every layer but the last stays in LDS: at most (S/2) x 2 x (S/2) entries before the last
+  constexpr int H = S / 2 > 0 ? S / 2 : 1;
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  __shared__ cd buf[2][H * 2 * H];
+  __shared__ Gate2 gates[kMaxRun];
+  const int ncore = run.core_hi - run.core_lo + 1;
+  const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
+  const int b = kXcds * (j / ncore) + xcd, k = run.core_lo + j % ncore;
+  if (b >= batch) return;
+  const int tid = threadIdx.x;
+  T* slot = state + ((size_t)b * n + k) * SLOT;
+  int Dp = bond_dim(n, chi, run.layer0, k - 1), Do = bond_dim(n, chi, run.layer0, k);
+  if (tid < run.count)  // one lane per layer: the gates' trigonometry runs side by side
+    gates[tid] = site_gate(kGateRyRz, k, theta + (size_t)tid * n, phi + (size_t)tid * n, nullptr);
+  {
+    const FastDiv fdo(Do);
+    for (int idx = tid; idx < Dp * 2 * Do; idx += kLayerThreads) {
+      const int row = fdo.q(idx), c = fdo.r(idx);
+      buf[0][idx] = to_cd(cx<T>{slot[2 * ((size_t)row * S + c)], slot[2 * ((size_t)row * S + c) + 1]});
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  bool bad = false;
+  for (int r = 0; r < run.count; ++r) {
+    const Gate2 g = gates[r];
+    const cd* src = buf[cur];
+    const int D = Do;
+    auto at = [&](int a, int s_, int c) { return src[(a * 2 + s_) * D + c]; };
+    if (r + 1 == run.count) {
+      bad = mpo_plain_site<S, T>(at, g, Dp, Do, slot, tid, kLayerThreads);
+    } else {
+      cd* dst = buf[cur ^ 1];
+      const int R = 2 * Do;
+      const FastDiv fr(R), fdp(Dp), fdo(Do);
+      for (int idx = tid; idx < 4 * Dp * R; idx += kLayerThreads) {
+        const int row = fr.q(idx), m = fr.r(idx), i = row >> 1, y = row & 1;
+        const int p = fdp.q(i), a = fdp.r(i), q = fdo.q(m), c = fdo.r(m);
+        dst[idx] = (q == y) ? gated_at(at, g, a, y ^ p, c) : cd{0.0, 0.0};
+      }
+      __syncthreads();
+      cur ^= 1;
+      Dp *= 2;
+      Do *= 2;
+    }
+  }
+  if (__any(bad) && tid == 0) atomicOr(status + b, kImgNonfinite);
+}
+
+// Length of the run of layers from `layer` (at most max_count) that can go through the two run
+// kernels: every layer keeps all its singular values, and some sites lie between the reduced
+// ends in all of them.  Fills `run`.  0 when the layer at `layer` cannot start such a run.
+int mpo_run(int n, int chi, int S, int layer, int max_count, MpoRun& run) {
+  if (g_exact_qr != kExactMpo || S > kMaxBond) return 0;
+  run.layer0 = layer;
+  run.core_lo = 0;
+  run.core_hi = n - 1;
+  int count = 0;
+  while (count < max_count && count < kMaxRun) {
+    const int l = layer + count;
+    MpoPlan p;
+    if (!layer_keeps_all(n, chi, l) ||
+        !mpo_plan(n, [&](int k) { return bond_dim(n, chi, l, k); },
+                  [&](int k) { return bond_dim(n, chi, l + 1, k); }, p))
+      break;
+    const int lo = std::max(run.core_lo, p.kl + 2), hi = std::min(run.core_hi, p.kr - 1);
+    if (lo > hi) break;
+    run.plan[count] = p;
+    run.core_lo = lo;
+    run.core_hi = hi;
+    ++count;
+  }
+  run.count = count;
+  return count;
+}
+
+// A second stream per device (default priority) so that the ends of a run, a chain of small
+// dependent steps, overlap the core launch: the caller's stream forks to it through an event
+// and joins it again before returning, so the caller sees one ordered step.  Created on first
+// use and kept until the process ends; the fork and join are serialised by a mutex.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+
+hipError_t side_stream(SideStream*& out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  SideStream& sd = g_side[dev];
+  if (!sd.stream) {
+    if ((e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  out = &sd;
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_mpo_run(T* state, int n, int chi, int S, const MpoRun& run, int batch,
+                          const double* theta, const double* phi, double* trunc_err, int* status,
+                          hipStream_t stream) {
+  const unsigned groups = (unsigned)((batch + kXcds - 1) / kXcds);
+  const unsigned ncore = (unsigned)(run.core_hi - run.core_lo + 1);
+  const dim3 block(kLayerThreads);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream* sd = nullptr;
+  hipError_t e = side_stream(sd);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(sd->fork, stream)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(sd->stream, sd->fork, 0)) != hipSuccess) return e;
+  switch (S) {
+#define ANOMPS_KR(SV)                                                                              \
+  case SV:                                                                                         \
+    hipLaunchKernelGGL((k_mpo_run_ends<SV, T>), dim3(kXcds * groups * 2), block, 0, sd->stream,    \
+                       state, n, chi, run, theta, phi, trunc_err, status, batch);                  \
+    if ((e = hipGetLastError()) != hipSuccess) break;                                              \
+    hipLaunchKernelGGL((k_mpo_run_core<SV, T>), dim3(kXcds * groups * ncore), block, 0, stream,    \
+                       state, n, chi, run, theta, phi, status, batch);                             \
+    e = hipGetLastError();                                                                         \
+    break;
+    ANOMPS_KR(2) ANOMPS_KR(4) ANOMPS_KR(8) ANOMPS_KR(16)
+#undef ANOMPS_KR
+    default: e = hipErrorInvalidValue;
+  }
+  // join even after a failed launch, so that the caller's stream never runs ahead of the side
+  const hipError_t e2 = hipEventRecord(sd->join, sd->stream);
+  const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(stream, sd->join, 0) : e2;
+  return e != hipSuccess ? e : e3;
+}
+
+// Applies `count` ladder layers: runs of exact layers through the run kernels, the others one
+// call of launch_layer each.  theta, phi: [count][n]; trunc_err: [count][batch][n-1] or null.
+template <typename T>
+hipError_t launch_layers(T* state, int n, int chi, int S, int layer, int count, int batch,
+                         const double* theta, const double* phi, double* trunc_err, int* status,
+                         hipStream_t stream) {
+  int r = 0;
+  while (r < count) {
+    const double* th = theta + (size_t)r * n;
+    const double* ph = phi + (size_t)r * n;
+    double* te = trunc_err ? trunc_err + (size_t)r * batch * (n - 1) : nullptr;
+    MpoRun run;
+    const int len = mpo_run(n, chi, S, layer + r, count - r, run);
+    hipError_t e;
+    if (len >= 2) {
+      e = launch_mpo_run<T>(state, n, chi, S, run, batch, th, ph, te, status, stream);
+    } else {
+      e = launch_layer<T>(state, n, chi, S, layer + r, batch, kLayerRyRzLadder, th, ph, nullptr,
+                          te, status, stream);
+    }
+    if (e != hipSuccess) return e;
+    r += len >= 2 ? len : 1;
+  }
+  return hipSuccess;
+}
+
 template hipError_t launch_encode<double>(double*, const double*, int, int, int, int*, hipStream_t);
 template hipError_t launch_encode<float>(float*, const double*, int, int, int, int*, hipStream_t);
 template hipError_t launch_layer<double>(double*, int, int, int, int, int, int, const double*,
                                          const double*, const double*, double*, int*, hipStream_t);
 template hipError_t launch_layer<float>(float*, int, int, int, int, int, int, const double*,
                                         const double*, const double*, double*, int*, hipStream_t);
+template hipError_t launch_layers<double>(double*, int, int, int, int, int, int, const double*,
+                                          const double*, double*, int*, hipStream_t);
+template hipError_t launch_layers<float>(float*, int, int, int, int, int, int, const double*,
+                                         const double*, double*, int*, hipStream_t);
 template hipError_t launch_encode_mixed<double>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_encode_mixed<float>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_layer_mixed<double>(const mps_request*, int, int, int, int*, int, hipStream_t);

@@ -32,7 +32,9 @@ def make_specs(mixed, anomps, cases, seed):
 
 def alone(anomps, sp):
     import torch
-    res = anomps.extract_features(sp.pixels[None], sp.theta, sp.phi, sp.pairs, sp.chi, sp.precision)
+    # one mps_apply_layer call per layer, the mixed table's own step structure
+    res = anomps.extract_features(sp.pixels[None], sp.theta, sp.phi, sp.pairs, sp.chi, sp.precision,
+                                  per_layer=True)
     torch.cuda.synchronize()
     return res[0].cpu().numpy()[0], int(res[1].cpu().numpy()[0])
 
