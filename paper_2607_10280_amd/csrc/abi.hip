@@ -290,13 +290,13 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
     else
       e = launch_measure_wide<float>((const float*)b->state, (float*)b->env, wide_ws(b, S), pairs,
                                      m, b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
+  } else if (S == 16) {
+    e = launch_measure16(b->state, b->env, pairs, m, b->n_sites, b->chi, L, b->batch, out,
+                         b->precision, stream);
   } else if (b->precision == MPS_PREC_FP64) {
     e = launch_envs<double, double>((const double*)b->state, (double*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)
       e = launch_pairs<double, double>((const double*)b->state, (const double*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
-  } else if (S == 16) {
-    e = launch_measure16((const float*)b->state, (float*)b->env, pairs, m, b->n_sites, b->chi, L,
-                         b->batch, (float*)out, b->precision == MPS_PREC_SPLIT_BF16, stream);
   } else {
     e = launch_envs<float, float>((const float*)b->state, (float*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)
@@ -409,10 +409,10 @@ int mps_pauli_pair_expect_mixed(const mps_request* reqs, const mps_mixed_plan* p
     if (!plan->count[k]) continue;
     const int S = bucket_slot(k), b0 = plan->begin[k], c = plan->count[k], ns = plan->max_sites[k];
     hipError_t e;
-    if (bucket_fp64(k))
+    if (S == 16)
+      e = launch_measure16_mixed(reqs, b0, c, ns, bucket_fp64(k), stream);
+    else if (bucket_fp64(k))
       e = launch_measure_mixed<double, double>(reqs, b0, c, ns, S, stream);
-    else if (S == 16)
-      e = launch_measure16_mixed(reqs, b0, c, ns, stream);
     else
       e = launch_measure_mixed<float, float>(reqs, b0, c, ns, S, stream);
     if (e != hipSuccess) return check_hip(e, "mixed measurement launch");

@@ -41,11 +41,11 @@ template <typename T, typename C>
 hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, int n, int chi,
                         int S, int layers, int batch, C* out, hipStream_t stream);
 
-// Matrix-core measurement for 16-wide slots (environments + pairs): FP32 products, or
-// split-BF16 products with FP32 accumulation.
-hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
-                            int chi, int layers, int batch, float* out, bool split_bf16,
-                            hipStream_t stream);
+// Matrix-core measurement for 16-wide slots (environments + pairs), by the batch's precision:
+// FP64 products (state, environments and outputs FP64), FP32 products, or split-BF16 products
+// with FP32 accumulation.
+hipError_t launch_measure16(const void* state, void* env, const int* pairs, int m, int n, int chi,
+                            int layers, int batch, void* out, int precision, hipStream_t stream);
 
 // Wide slots (S = 32, 64, 128; wide.hip): the same layer and measurement with one 256-lane
 // workgroup per image and the per-bond matrices in an FP64 workspace of
@@ -71,7 +71,7 @@ template <typename T, typename C>
 hipError_t launch_measure_mixed(const mps_request* reqs, int begin, int count, int max_sites,
                                 int S, hipStream_t stream);
 hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count, int max_sites,
-                                  hipStream_t stream);
+                                  bool fp64, hipStream_t stream);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t stream);
 
 template <typename R>

@@ -9,7 +9,7 @@
 //
 // Operand convention (one wave, lane l, g = l/16): for k-chunk kc the lane supplies
 //   A-operand value  A[l%16][4g+kc],   B-operand value  B[4g+kc][l%16],
-// and owns accumulator entries D[4g+r][l%16], r = 0..3.  Because the accumulator layout equals
+// and owns accumulator entries D[4g+r][l%16], r = 0..3 (FP64: see kidx).  Because the accumulator layout equals
 // the B-operand layout (chunk kc <-> entry r), a product can feed the right factor of the next
 // product directly from registers; an accumulator holding M^T is the A-operand of M, so
 // environments and carried blocks are kept transposed and no product goes through LDS.  Site
@@ -27,24 +27,49 @@ namespace anomps {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-using cf = cx<float>;
+typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int W = 64;        // one wavefront per workgroup
 constexpr int NXCD = 8;
 constexpr int kMaxTargets16 = 256;
 
-struct Acc {
-  f4 re, im;
+// How a 16x16x16 complex product runs on the matrix cores:
+//  kMmaGauss     FP32, three real products (v_mfma_f32_16x16x4f32),
+//  kMmaSplitBf16 FP32 operands split into two bf16 parts (v_mfma_f32_16x16x16bf16_1k),
+//  kMmaF64       FP64, four real products (v_mfma_f64_16x16x4f64; its accumulator rows are
+//                interleaved differently, see kidx).
+enum : int { kMmaGauss = 0, kMmaSplitBf16 = 1, kMmaF64 = 2 };
+template <int MODE>
+struct MmaReal {
+  using type = float;
+  using v4 = f4;
+};
+template <>
+struct MmaReal<kMmaF64> {
+  using type = double;
+  using v4 = d4;
 };
 
-__device__ __forceinline__ Acc acc_zero() {
-  Acc a;
-  a.re = f4{0.f, 0.f, 0.f, 0.f};
-  a.im = f4{0.f, 0.f, 0.f, 0.f};
+template <typename V>
+struct AccT {
+  V re, im;
+};
+template <int MODE>
+using Acc = AccT<typename MmaReal<MODE>::v4>;
+
+template <int MODE>
+__device__ __forceinline__ Acc<MODE> acc_zero() {
+  using R = typename MmaReal<MODE>::type;
+  Acc<MODE> a;
+  a.re = typename MmaReal<MODE>::v4{R(0), R(0), R(0), R(0)};
+  a.im = a.re;
   return a;
 }
 
 __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 typedef short s4 __attribute__((ext_vector_type(4)));
@@ -82,9 +107,9 @@ __device__ __forceinline__ f4 mfma_split(const Split4& a, const Split4& b, f4 c)
 
 // C += A B with per-lane operand values for the four k-chunks (entry kc of the lane holds
 // k = 4g + kc, which is also the element order of a 16x16x16 bf16 operand).
-template <bool SPLIT>
-__device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]) {
-  if constexpr (!SPLIT) {
+template <int MODE, typename C>
+__device__ __forceinline__ void cgemm(Acc<MODE>& c, const C (&a)[4], const C (&b)[4]) {
+  if constexpr (MODE == kMmaGauss) {
     // Three real products (Gauss): re = Ar Br - Ai Bi, im = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi,
     // as three independent chains of four MFMAs.
     f4 t1 = f4{0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
@@ -96,6 +121,15 @@ __device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]
     }
     c.re += t1 - t2;
     c.im += t3 - t1 - t2;
+  } else if constexpr (MODE == kMmaF64) {
+    // Four real products accumulated in place: no combination step and no cancellation.
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      c.re = mfma(a[kc].re, b[kc].re, c.re);
+      c.re = mfma(-a[kc].im, b[kc].im, c.re);
+      c.im = mfma(a[kc].re, b[kc].im, c.im);
+      c.im = mfma(a[kc].im, b[kc].re, c.im);
+    }
   } else {
     const Split4 ar = split4(a[0].re, a[1].re, a[2].re, a[3].re, false);
     const Split4 ai = split4(a[0].im, a[1].im, a[2].im, a[3].im, false);
@@ -110,69 +144,86 @@ __device__ __forceinline__ void cgemm(Acc& c, const cf (&a)[4], const cf (&b)[4]
 }
 
 // Accumulator -> B-operand values (chunk kc <-> entry r).
-__device__ __forceinline__ void acc_as_b(const Acc& c, cf (&b)[4]) {
+template <typename V, typename C>
+__device__ __forceinline__ void acc_as_b(const AccT<V>& c, C (&b)[4]) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) b[r] = cf{c.re[r], c.im[r]};
+  for (int r = 0; r < 4; ++r) b[r] = C{c.re[r], c.im[r]};
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
+// The k index that lane group g (= l/16) covers in the product's k-chunk kc.  The FP32 and bf16
+// instructions leave accumulator entry r of lane l at row 4g + r, so chunk kc takes k = 4g + kc;
+// the FP64 instruction leaves it at row g + 4r, so there chunk kc takes k = g + 4kc.  Either way
+// accumulator entry r of lane l is the B-operand value of chunk r, and every load and store
+// below uses the same map.
+template <typename R>
+__device__ __forceinline__ int kidx(int kc, int g) {
+  if constexpr (sizeof(R) == 8) return g + 4 * kc;
+  return 4 * g + kc;
+}
+
 // Operand registers of the two physical slices of a site tensor (Dl x 2 x Dr, slot stride 16),
 // zero outside the Dl x Dr corner:
-//   column form a[u][kc] = A_u[4g+kc][l%16]  (B-operand of A_u, A-operand of A_u^T)
-//   row form    a[u][kc] = A_u[l%16][4g+kc]  (A-operand of A_u, B-operand of A_u^T)
+//   column form a[u][kc] = A_u[k][l%16]  (B-operand of A_u, A-operand of A_u^T)
+//   row form    a[u][kc] = A_u[l%16][k]  (A-operand of A_u, B-operand of A_u^T),  k = kidx(kc, g)
+template <typename R>
 struct SiteOps {
-  cf a[2][4];
-  __device__ __forceinline__ void load(const float* slot, int Dl, int Dr, bool row) {
+  cx<R> a[2][4];
+  __device__ __forceinline__ void load(const R* slot, int Dl, int Dr, bool row) {
     const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) {
-        const int c = row ? i16 : 4 * g + kc, e = row ? 4 * g + kc : i16;
+        const int kk = kidx<R>(kc, g), c = row ? i16 : kk, e = row ? kk : i16;
         const int idx = (c * 2 + u) * 16 + e;
-        const cf v{slot[2 * idx], slot[2 * idx + 1]};
-        a[u][kc] = (c < Dl && e < Dr) ? v : cf{0.f, 0.f};
+        const cx<R> v{slot[2 * idx], slot[2 * idx + 1]};
+        a[u][kc] = (c < Dl && e < Dr) ? v : cx<R>{R(0), R(0)};
       }
   }
 };
 
 // Row form (A-operand) of a 16x16 environment tile E[x][y] stored at x*16 + y.
-__device__ __forceinline__ void ld_env_row(const float* t, cf (&v)[4]) {
+template <typename R>
+__device__ __forceinline__ void ld_env_row(const R* t, cx<R> (&v)[4]) {
   const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
 #pragma unroll
   for (int kc = 0; kc < 4; ++kc) {
-    const int idx = i16 * 16 + 4 * g + kc;
-    v[kc] = cf{t[2 * idx], t[2 * idx + 1]};
+    const int idx = i16 * 16 + kidx<R>(kc, g);
+    v[kc] = cx<R>{t[2 * idx], t[2 * idx + 1]};
   }
 }
 
-__device__ __forceinline__ void conj4(const cf (&a)[4], cf (&b)[4]) {
+template <typename C>
+__device__ __forceinline__ void conj4(const C (&a)[4], C (&b)[4]) {
 #pragma unroll
-  for (int kc = 0; kc < 4; ++kc) b[kc] = cf{a[kc].re, -a[kc].im};
+  for (int kc = 0; kc < 4; ++kc) b[kc] = C{a[kc].re, -a[kc].im};
 }
 
-// A matrix M is carried transposed in the accumulator: the lane then holds M^T[4g+r][l%16] =
-// M[l%16][4g+r], which is the A-operand of M, so a chain of products never leaves registers.
+// A matrix M is carried transposed in the accumulator: the lane then holds M^T[k][l%16] =
+// M[l%16][k] (k = kidx(r, g)), which is the A-operand of M, so a chain of products never
+// leaves registers.
 //
 // Left transfer E' = sum_u A_u^T E conj(A_u) with E given as its A-operand (row form):
 // X_u = E conj(A_u), then E'^T = sum_u X_u^T A_u (the accumulator of X_u is the A-operand of
 // X_u^T).  a = column forms of A_0, A_1.  Returns E'^T.
-template <bool SPLIT>
-__device__ __forceinline__ Acc left_transfer_t(const cf (&e)[4], const cf (&a)[2][4]) {
-  Acc out = acc_zero();
+template <int MODE, typename C>
+__device__ __forceinline__ Acc<MODE> left_transfer_t(const C (&e)[4], const C (&a)[2][4]) {
+  Acc<MODE> out = acc_zero<MODE>();
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    cf ac[4], xa[4];
+    C ac[4], xa[4];
     conj4(a[u], ac);
-    Acc x = acc_zero();
-    cgemm<SPLIT>(x, e, ac);
+    Acc<MODE> x = acc_zero<MODE>();
+    cgemm<MODE>(x, e, ac);
     acc_as_b(x, xa);
-    cgemm<SPLIT>(out, xa, a[u]);
+    cgemm<MODE>(out, xa, a[u]);
   }
   return out;
 }
@@ -182,26 +233,30 @@ __device__ __forceinline__ Acc left_transfer_t(const cf (&e)[4], const cf (&a)[2
 // ------------------------------------------------------------------------- environments
 // One image: st = its n slots, ev = its environment block of this side ([n+1][16][16]).  The
 // environment is carried transposed in registers; tiles E[x][y] are stored at x*16 + y.
-template <bool SPLIT>
-__device__ __forceinline__ void env16_image(const float* st, float* ev, int n, int chi, int layers, int side) {
+template <int MODE>
+__device__ __forceinline__ void env16_image(const typename MmaReal<MODE>::type* st,
+                                            typename MmaReal<MODE>::type* ev, int n, int chi,
+                                            int layers, int side) {
+  using R = typename MmaReal<MODE>::type;
+  using C = cx<R>;
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
   const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
-  Acc e = acc_zero();  // the 1 x 1 identity
-  if (l == 0) e.re[0] = 1.f;
+  Acc<MODE> e = acc_zero<MODE>();  // the 1 x 1 identity
+  if (l == 0) e.re[0] = R(1);
   auto store_env = [&](int k) {
-    float* dst = ev + (size_t)k * ETILE;
+    R* dst = ev + (size_t)k * ETILE;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int idx = i16 * 16 + 4 * g + r;
+      const int idx = i16 * 16 + kidx<R>(r, g);
       dst[2 * idx] = e.re[r];
       dst[2 * idx + 1] = e.im[r];
     }
   };
-  SiteOps cur, nxt;
+  SiteOps<R> cur, nxt;
   const bool right = side != 0;
-  auto fetch = [&](int t, SiteOps& o) {
+  auto fetch = [&](int t, SiteOps<R>& o) {
     const int k = right ? n - 1 - t : t;
     o.load(st + (size_t)k * SLOT, dim(k - 1), dim(k), right);
   };
@@ -209,22 +264,22 @@ __device__ __forceinline__ void env16_image(const float* st, float* ev, int n, i
   fetch(0, cur);
   for (int t = 0; t < n; ++t) {
     if (t + 1 < n) fetch(t + 1, nxt);
-    cf eo[4];
+    C eo[4];
     acc_as_b(e, eo);
     if (!right) {
       // L_{k+1} = sum_u A_u^T L_k conj(A_u)
-      e = left_transfer_t<SPLIT>(eo, cur.a);
+      e = left_transfer_t<MODE>(eo, cur.a);
     } else {
       // R_k = sum_s A_s R_{k+1} A_s^H: Y_s = R A_s^H, R_k^T = sum_s Y_s^T A_s^T (row forms)
-      Acc o = acc_zero();
+      Acc<MODE> o = acc_zero<MODE>();
 #pragma unroll
       for (int s_ = 0; s_ < 2; ++s_) {
-        cf ah[4], ya[4];
+        C ah[4], ya[4];
         conj4(cur.a[s_], ah);
-        Acc y = acc_zero();
-        cgemm<SPLIT>(y, eo, ah);
+        Acc<MODE> y = acc_zero<MODE>();
+        cgemm<MODE>(y, eo, ah);
         acc_as_b(y, ya);
-        cgemm<SPLIT>(o, ya, cur.a[s_]);
+        cgemm<MODE>(o, ya, cur.a[s_]);
       }
       e = o;
     }
@@ -244,14 +299,16 @@ __device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
   }
 }
 
-__device__ __forceinline__ cf cmul_f(cf a, cf b) { return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <typename C>
+__device__ __forceinline__ C cmul_c(C a, C b) { return C{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
 // Operands fetched one step ahead: the site (column form to carry through it and to open,
 // row form to close) and, at the open, L_i.  R_{j+1} and L_j are read at the close itself:
 // prefetching them too costs a register spill at three waves per SIMD, which is slower.
+template <typename R>
 struct PairStep {
-  SiteOps s;
-  cf li[4];
+  SiteOps<R> s;
+  cx<R> li[4];
 };
 
 // One image and one start site i: st = its n slots, evL = its environments ([2][n+1][16][16]),
@@ -260,20 +317,24 @@ struct PairStep {
 //  carry k:     F <- sum_u A_u^T F conj(A_u) for F^00 and F^01
 //  close at j:  Y_t' = R_{j+1} A_t'^H,  G^{tt'} = A_t Y_t',  F^11 = L_j - F^00
 //               rho[(s,t),(s',t')] = sum_{d,d'} F^{ss'}[d][d'] G^{tt'}[d][d']
-// F^{ss'} and G^{tt'} are held transposed (lane: entry (x, y) = (l%16, 4g+r)), G^01 also
+// F^{ss'} and G^{tt'} are held transposed (lane: entry (x, y) = (l%16, kidx(r, g))), G^01 also
 // untransposed (entry (y, x)), so every upper-triangle entry of the Hermitian rho is a sum of
 // lane-local products: only F^{ss'} with s <= s' appear there, and G^10[x][y] = conj(G^01[y][x]).
-template <bool SPLIT>
-__device__ __forceinline__ void pairs16_image(const float* st, const float* evL, const int* pairs, int m, int n,
-                              int chi, int layers, int i, float* out) {
+template <int MODE>
+__device__ __forceinline__ void pairs16_image(const typename MmaReal<MODE>::type* st,
+                                              const typename MmaReal<MODE>::type* evL,
+                                              const int* pairs, int m, int n, int chi, int layers,
+                                              int i, typename MmaReal<MODE>::type* out) {
+  using R = typename MmaReal<MODE>::type;
+  using C = cx<R>;
   __shared__ int tq[kMaxTargets16], tj[kMaxTargets16];
   __shared__ int cnt;
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
   const int l = threadIdx.x;
-  const float* evR = evL + (size_t)(n + 1) * ETILE;
+  const R* evR = evL + (size_t)(n + 1) * ETILE;
   auto dim = [&](int k) { return bond_dim(n, chi, layers, k); };
-  const float qnan = __builtin_nanf("");
+  const R qnan = R(__builtin_nan(""));
 
   if (l == 0) cnt = 0;
   __syncthreads();
@@ -325,106 +386,107 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
     nk = cc < j ? 0 : 1;
     ns = cc < j ? cc : j;
   };
-  auto fetch = [&](int kind, int site, PairStep& p) {
+  auto fetch = [&](int kind, int site, PairStep<R>& p) {
     p.s.load(st + (size_t)site * SLOT, dim(site - 1), dim(site), kind == 1);
     if (kind == 2) ld_env_row(evL + (size_t)site * ETILE, p.li);
   };
-  PairStep pa, pb;
+  PairStep<R> pa, pb;
   int kind = 2, site = i;
   fetch(kind, site, pa);
-  Acc F0 = acc_zero(), F1 = acc_zero();  // F^00, F^01, transposed
+  Acc<MODE> F0 = acc_zero<MODE>(), F1 = acc_zero<MODE>();  // F^00, F^01, transposed
   while (kind >= 0) {
     int nk, ns;
     successor(kind, site, nk, ns);
     if (nk >= 0) fetch(nk, ns, pb);
     if (kind == 2) {
-      cf ac[4], xa[4];
+      C ac[4], xa[4];
       conj4(pa.s.a[0], ac);
-      Acc x0 = acc_zero();
-      cgemm<SPLIT>(x0, pa.li, ac);
+      Acc<MODE> x0 = acc_zero<MODE>();
+      cgemm<MODE>(x0, pa.li, ac);
       acc_as_b(x0, xa);
-      F0 = acc_zero();
-      cgemm<SPLIT>(F0, xa, pa.s.a[0]);
+      F0 = acc_zero<MODE>();
+      cgemm<MODE>(F0, xa, pa.s.a[0]);
       conj4(pa.s.a[1], ac);
-      Acc x1 = acc_zero();
-      cgemm<SPLIT>(x1, pa.li, ac);
+      Acc<MODE> x1 = acc_zero<MODE>();
+      cgemm<MODE>(x1, pa.li, ac);
       acc_as_b(x1, xa);
-      F1 = acc_zero();
-      cgemm<SPLIT>(F1, xa, pa.s.a[0]);
+      F1 = acc_zero<MODE>();
+      cgemm<MODE>(F1, xa, pa.s.a[0]);
     } else if (kind == 0) {
-      cf fo[4];
+      C fo[4];
       acc_as_b(F0, fo);
-      const Acc n0 = left_transfer_t<SPLIT>(fo, pa.s.a);
+      const Acc<MODE> n0 = left_transfer_t<MODE>(fo, pa.s.a);
       acc_as_b(F1, fo);
-      F1 = left_transfer_t<SPLIT>(fo, pa.s.a);
+      F1 = left_transfer_t<MODE>(fo, pa.s.a);
       F0 = n0;
     } else {
-      cf rj[4], lj[4];
+      C rj[4], lj[4];
       ld_env_row(evR + (size_t)(site + 1) * ETILE, rj);
       ld_env_row(evL + (size_t)site * ETILE, lj);
       // Y_t' = R A_t'^H (B-operand conj of the row form); G^{tt'T} = Y_t'^T A_t^T; G^01 = A_0 Y_1
-      cf ah[4], y0a[4], y1a[4];
+      C ah[4], y0a[4], y1a[4];
       conj4(pa.s.a[0], ah);
-      Acc y = acc_zero();
-      cgemm<SPLIT>(y, rj, ah);
+      Acc<MODE> y = acc_zero<MODE>();
+      cgemm<MODE>(y, rj, ah);
       acc_as_b(y, y0a);
       conj4(pa.s.a[1], ah);
-      y = acc_zero();
-      cgemm<SPLIT>(y, rj, ah);
+      y = acc_zero<MODE>();
+      cgemm<MODE>(y, rj, ah);
       acc_as_b(y, y1a);
-      Acc g00 = acc_zero(), g01 = acc_zero(), g11 = acc_zero(), h01 = acc_zero();
-      cgemm<SPLIT>(g00, y0a, pa.s.a[0]);
-      cgemm<SPLIT>(g01, y1a, pa.s.a[0]);
-      cgemm<SPLIT>(g11, y1a, pa.s.a[1]);
-      cgemm<SPLIT>(h01, pa.s.a[0], y1a);
+      Acc<MODE> g00 = acc_zero<MODE>(), g01 = acc_zero<MODE>(), g11 = acc_zero<MODE>(),
+                h01 = acc_zero<MODE>();
+      cgemm<MODE>(g00, y0a, pa.s.a[0]);
+      cgemm<MODE>(g01, y1a, pa.s.a[0]);
+      cgemm<MODE>(g11, y1a, pa.s.a[1]);
+      cgemm<MODE>(h01, pa.s.a[0], y1a);
       // upper triangle of rho, entry (row, col) with row = s*2+t, col = s'*2+t'
-      float d00 = 0.f, d11 = 0.f, d22 = 0.f, d33 = 0.f;
-      cf e01{0.f, 0.f}, e02{0.f, 0.f}, e03{0.f, 0.f}, e12{0.f, 0.f}, e13{0.f, 0.f}, e23{0.f, 0.f};
+      R d00 = 0, d11 = 0, d22 = 0, d33 = 0;
+      C e01{0, 0}, e02{0, 0}, e03{0, 0}, e12{0, 0}, e13{0, 0}, e23{0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const cf f00{F0.re[r], F0.im[r]}, f01{F1.re[r], F1.im[r]};
-        const cf f11{lj[r].re - f00.re, lj[r].im - f00.im};
-        const cf G00{g00.re[r], g00.im[r]}, G01{g01.re[r], g01.im[r]}, G11{g11.re[r], g11.im[r]};
-        const cf G10{h01.re[r], -h01.im[r]};
+        const C f00{F0.re[r], F0.im[r]}, f01{F1.re[r], F1.im[r]};
+        const C f11{lj[r].re - f00.re, lj[r].im - f00.im};
+        const C G00{g00.re[r], g00.im[r]}, G01{g01.re[r], g01.im[r]}, G11{g11.re[r], g11.im[r]};
+        const C G10{h01.re[r], -h01.im[r]};
         d00 += f00.re * G00.re - f00.im * G00.im;
         d11 += f00.re * G11.re - f00.im * G11.im;
         d22 += f11.re * G00.re - f11.im * G00.im;
         d33 += f11.re * G11.re - f11.im * G11.im;
-        const cf p01 = cmul_f(f00, G01), p02 = cmul_f(f01, G00), p03 = cmul_f(f01, G01);
-        const cf p12 = cmul_f(f01, G10), p13 = cmul_f(f01, G11), p23 = cmul_f(f11, G01);
-        e01 = cf{e01.re + p01.re, e01.im + p01.im};
-        e02 = cf{e02.re + p02.re, e02.im + p02.im};
-        e03 = cf{e03.re + p03.re, e03.im + p03.im};
-        e12 = cf{e12.re + p12.re, e12.im + p12.im};
-        e13 = cf{e13.re + p13.re, e13.im + p13.im};
-        e23 = cf{e23.re + p23.re, e23.im + p23.im};
+        const C p01 = cmul_c(f00, G01), p02 = cmul_c(f01, G00), p03 = cmul_c(f01, G01);
+        const C p12 = cmul_c(f01, G10), p13 = cmul_c(f01, G11), p23 = cmul_c(f11, G01);
+        e01 = C{e01.re + p01.re, e01.im + p01.im};
+        e02 = C{e02.re + p02.re, e02.im + p02.im};
+        e03 = C{e03.re + p03.re, e03.im + p03.im};
+        e12 = C{e12.re + p12.re, e12.im + p12.im};
+        e13 = C{e13.re + p13.re, e13.im + p13.im};
+        e23 = C{e23.re + p23.re, e23.im + p23.im};
       }
-      d00 = wave_sum_f(d00);
-      d11 = wave_sum_f(d11);
-      d22 = wave_sum_f(d22);
-      d33 = wave_sum_f(d33);
-      e01 = cf{wave_sum_f(e01.re), wave_sum_f(e01.im)};
-      e02 = cf{wave_sum_f(e02.re), wave_sum_f(e02.im)};
-      e03 = cf{wave_sum_f(e03.re), wave_sum_f(e03.im)};
-      e12 = cf{wave_sum_f(e12.re), wave_sum_f(e12.im)};
-      e13 = cf{wave_sum_f(e13.re), wave_sum_f(e13.im)};
-      e23 = cf{wave_sum_f(e23.re), wave_sum_f(e23.im)};
+      d00 = wave_sum(d00);
+      d11 = wave_sum(d11);
+      d22 = wave_sum(d22);
+      d33 = wave_sum(d33);
+      e01 = C{wave_sum(e01.re), wave_sum(e01.im)};
+      e02 = C{wave_sum(e02.re), wave_sum(e02.im)};
+      e03 = C{wave_sum(e03.re), wave_sum(e03.im)};
+      e12 = C{wave_sum(e12.re), wave_sum(e12.im)};
+      e13 = C{wave_sum(e13.re), wave_sum(e13.im)};
+      e23 = C{wave_sum(e23.re), wave_sum(e23.im)};
       // full rho (row-major 4x4): lower triangle = conjugate transpose
-      const cf rho[16] = {cf{d00, 0.f}, e01, e02, e03,
-                          cf{e01.re, -e01.im}, cf{d11, 0.f}, e12, e13,
-                          cf{e02.re, -e02.im}, cf{e12.re, -e12.im}, cf{d22, 0.f}, e23,
-                          cf{e03.re, -e03.im}, cf{e13.re, -e13.im}, cf{e23.re, -e23.im}, cf{d33, 0.f}};
+      const C rho[16] = {C{d00, 0}, e01, e02, e03,
+                         C{e01.re, -e01.im}, C{d11, 0}, e12, e13,
+                         C{e02.re, -e02.im}, C{e12.re, -e12.im}, C{d22, 0}, e23,
+                         C{e03.re, -e03.im}, C{e13.re, -e13.im}, C{e23.re, -e23.im}, C{d33, 0}};
       if (l < 15) {
         // <P_a (x) P_c> = sum_{s,t,s',t'} rho[(s,t),(s',t')] P_a[s'][s] P_c[t'][t]
         const int al = l + 1, pa_ = al >> 2, pc = al & 3;
-        float acc = 0.f;
+        R acc = 0;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
-          const float ar = pauli_re(pa_, sp, s, false), ai = pauli_re(pa_, sp, s, true);
-          const float cr = pauli_re(pc, tp, t, false), ci = pauli_re(pc, tp, t, true);
-          const float wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
-          const cf rv = rho[(s * 2 + t) * 4 + sp * 2 + tp];
+          const R ar = pauli_re(pa_, sp, s, false), ai = pauli_re(pa_, sp, s, true);
+          const R cr = pauli_re(pc, tp, t, false), ci = pauli_re(pc, tp, t, true);
+          const R wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
+          const C rv = rho[(s * 2 + t) * 4 + sp * 2 + tp];
           acc += rv.re * wr - rv.im * wi;
         }
         out[(size_t)uniform_int(tq[x]) * 15 + l] = acc;
@@ -440,48 +502,68 @@ __device__ __forceinline__ void pairs16_image(const float* st, const float* evL,
 
 // Workgroup w runs on XCD w % 8; all workgroups of one image sit on the same XCD so that its
 // state and environments are shared through that XCD's L2.
-template <bool SPLIT>
-__global__ __launch_bounds__(W) void k_env16(const float* state, float* env, int n, int chi,
+template <int MODE>
+__global__ __launch_bounds__(W) void k_env16(const typename MmaReal<MODE>::type* state,
+                                              typename MmaReal<MODE>::type* env, int n, int chi,
                                               int layers, int batch) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
   const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
   const int b = NXCD * (j >> 1) + xcd, side = j & 1;
   if (b >= batch) return;
-  env16_image<SPLIT>(state + (size_t)b * n * SLOT, env + ((size_t)b * 2 + side) * (n + 1) * ETILE, n, chi,
-              layers, side);
+  env16_image<MODE>(state + (size_t)b * n * SLOT, env + ((size_t)b * 2 + side) * (n + 1) * ETILE,
+                    n, chi, layers, side);
 }
 
-// Three waves per SIMD (168 registers, no spill): measured faster than two or four, the extra
-// wave hiding MFMA and load latency.
-template <bool SPLIT>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pairs16(const float* state, const float* env,
-                                                const int* pairs, int m, int n, int chi,
-                                                int layers, int batch, float* out) {
+template <int MODE>
+__device__ __forceinline__ void pairs16_block(const typename MmaReal<MODE>::type* state,
+                                              const typename MmaReal<MODE>::type* env,
+                                              const int* pairs, int m, int n, int chi, int layers,
+                                              int batch, typename MmaReal<MODE>::type* out) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
   const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
   const int b = NXCD * (jw / (n - 1)) + xcd, i = jw % (n - 1);
   if (b >= batch) return;
-  pairs16_image<SPLIT>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs, m, n,
-                chi, layers, i, out + (size_t)b * m * 15);
+  pairs16_image<MODE>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs,
+                      m, n, chi, layers, i, out + (size_t)b * m * 15);
 }
 
-// Mixed request tables (one bucket: S = 16, FP32), with the same XCD grouping by request.
+// FP32 modes: three waves per SIMD (168 registers, no spill), measured faster than two or four,
+// the extra wave hiding MFMA and load latency.
+template <int MODE>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pairs16(
+    const float* state, const float* env, const int* pairs, int m, int n, int chi, int layers,
+    int batch, float* out) {
+  pairs16_block<MODE>(state, env, pairs, m, n, chi, layers, batch, out);
+}
+
+// FP64: every operand and accumulator takes twice the registers.
+__global__ __launch_bounds__(W) void k_pairs16_f64(const double* state, const double* env,
+                                                   const int* pairs, int m, int n, int chi,
+                                                   int layers, int batch, double* out) {
+  pairs16_block<kMmaF64>(state, env, pairs, m, n, chi, layers, batch, out);
+}
+
+// Mixed request tables (one bucket: S = 16, FP32 or FP64), with the same XCD grouping by request.
+template <int MODE>
 __global__ __launch_bounds__(W) void k_env16_mixed(const mps_request* reqs, int begin, int count) {
+  using R = typename MmaReal<MODE>::type;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
   const int w = blockIdx.x, xcd = w % NXCD, j = w / NXCD;
   const int r = NXCD * (j >> 1) + xcd, side = j & 1;
   if (r >= count) return;
   const mps_request* q = reqs + begin + r;
   const int n = uniform_int(q->n_sites), layers = uniform_int(uniform_ptr(q->ctrl)[0]);
-  env16_image<false>(uniform_ptr((const float*)q->state),
-              uniform_ptr((float*)q->env) + (size_t)side * (n + 1) * ETILE, n, uniform_int(q->chi),
-              layers, side);
+  env16_image<MODE>(uniform_ptr((const R*)q->state),
+                    uniform_ptr((R*)q->env) + (size_t)side * (n + 1) * ETILE, n,
+                    uniform_int(q->chi), layers, side);
 }
 
+template <int MODE>
 __global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, int begin, int count,
                                                       int max_sites) {
+  using R = typename MmaReal<MODE>::type;
   const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
   const int r = NXCD * (jw / (max_sites - 1)) + xcd, i = jw % (max_sites - 1);
   if (r >= count) return;
@@ -489,41 +571,54 @@ __global__ __launch_bounds__(W) void k_pairs16_mixed(const mps_request* reqs, in
   const int n = uniform_int(q->n_sites), m = uniform_int(q->n_pairs);
   if (i >= n - 1 || m == 0) return;
   const int layers = uniform_int(uniform_ptr(q->ctrl)[0]);
-  pairs16_image<false>(uniform_ptr((const float*)q->state), uniform_ptr((const float*)q->env),
-                uniform_ptr(q->pairs), m, n, uniform_int(q->chi), layers, i,
-                uniform_ptr((float*)q->out));
+  pairs16_image<MODE>(uniform_ptr((const R*)q->state), uniform_ptr((const R*)q->env),
+                      uniform_ptr(q->pairs), m, n, uniform_int(q->chi), layers, i,
+                      uniform_ptr((R*)q->out));
 }
 
 hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count, int max_sites,
-                                  hipStream_t stream) {
+                                  bool fp64, hipStream_t stream) {
   if (count == 0) return hipSuccess;
   const int groups = (count + NXCD - 1) / NXCD;
-  hipLaunchKernelGGL(k_env16_mixed, dim3((unsigned)(NXCD * groups * 2)), dim3(W), 0, stream, reqs,
-                     begin, count);
-  hipLaunchKernelGGL(k_pairs16_mixed, dim3((unsigned)((size_t)NXCD * groups * (max_sites - 1))),
-                     dim3(W), 0, stream, reqs, begin, count, max_sites);
+  const dim3 genv((unsigned)(NXCD * groups * 2));
+  const dim3 gpair((unsigned)((size_t)NXCD * groups * (max_sites - 1)));
+  if (fp64) {
+    hipLaunchKernelGGL((k_env16_mixed<kMmaF64>), genv, dim3(W), 0, stream, reqs, begin, count);
+    hipLaunchKernelGGL((k_pairs16_mixed<kMmaF64>), gpair, dim3(W), 0, stream, reqs, begin, count,
+                       max_sites);
+  } else {
+    hipLaunchKernelGGL((k_env16_mixed<kMmaGauss>), genv, dim3(W), 0, stream, reqs, begin, count);
+    hipLaunchKernelGGL((k_pairs16_mixed<kMmaGauss>), gpair, dim3(W), 0, stream, reqs, begin,
+                       count, max_sites);
+  }
   return hipGetLastError();
 }
 
-template <bool SPLIT>
-static hipError_t launch_measure16_t(const float* state, float* env, const int* pairs, int m, int n,
-                                     int chi, int layers, int batch, float* out, hipStream_t stream) {
+hipError_t launch_measure16(const void* state, void* env, const int* pairs, int m, int n, int chi,
+                            int layers, int batch, void* out, int precision, hipStream_t stream) {
   const int groups = (batch + NXCD - 1) / NXCD;
-  hipLaunchKernelGGL((k_env16<SPLIT>), dim3((unsigned)(NXCD * groups * 2)), dim3(W), 0, stream,
-                     state, env, n, chi, layers, batch);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || m == 0) return e;
-  hipLaunchKernelGGL((k_pairs16<SPLIT>), dim3((unsigned)((size_t)NXCD * groups * (n - 1))), dim3(W),
-                     0, stream, state, (const float*)env, pairs, m, n, chi, layers, batch, out);
+  const dim3 genv((unsigned)(NXCD * groups * 2)), gpair((unsigned)((size_t)NXCD * groups * (n - 1)));
+  hipError_t e;
+  if (precision == MPS_PREC_FP64) {
+    hipLaunchKernelGGL((k_env16<kMmaF64>), genv, dim3(W), 0, stream, (const double*)state,
+                       (double*)env, n, chi, layers, batch);
+    if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
+    hipLaunchKernelGGL(k_pairs16_f64, gpair, dim3(W), 0, stream, (const double*)state,
+                       (const double*)env, pairs, m, n, chi, layers, batch, (double*)out);
+  } else if (precision == MPS_PREC_SPLIT_BF16) {
+    hipLaunchKernelGGL((k_env16<kMmaSplitBf16>), genv, dim3(W), 0, stream, (const float*)state,
+                       (float*)env, n, chi, layers, batch);
+    if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
+    hipLaunchKernelGGL((k_pairs16<kMmaSplitBf16>), gpair, dim3(W), 0, stream, (const float*)state,
+                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out);
+  } else {
+    hipLaunchKernelGGL((k_env16<kMmaGauss>), genv, dim3(W), 0, stream, (const float*)state,
+                       (float*)env, n, chi, layers, batch);
+    if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
+    hipLaunchKernelGGL((k_pairs16<kMmaGauss>), gpair, dim3(W), 0, stream, (const float*)state,
+                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out);
+  }
   return hipGetLastError();
-}
-
-hipError_t launch_measure16(const float* state, float* env, const int* pairs, int m, int n,
-                            int chi, int layers, int batch, float* out, bool split_bf16,
-                            hipStream_t stream) {
-  return split_bf16
-      ? launch_measure16_t<true>(state, env, pairs, m, n, chi, layers, batch, out, stream)
-      : launch_measure16_t<false>(state, env, pairs, m, n, chi, layers, batch, out, stream);
 }
 
 }  // namespace anomps
