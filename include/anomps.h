@@ -177,14 +177,16 @@ int mps_apply_layers(mps_batch* b, int32_t count, const double* theta, const dou
  *    those sites become identity tensors and the product of their B's is carried into the
  *    first site with a full bond.  No site is orthonormalised (the norm is the input's, the
  *    layer being unitary); the measurement contracts both environments and needs no gauge.
- *    Slots wider than 16 take these layers like the truncating ones (next paragraph).
+ *    The brickwork program of mps_apply_layer_program takes the same form (one bit per bond:
+ *    an even site passes its input bit, an odd site its output bit) unless its two end carries
+ *    land on one site.  Slots wider than 16 take these layers like the truncating ones (next
+ *    paragraph).
  *  MPS_EXACT_QR: one left-to-right sweep; each two-site matrix Theta' is split exactly, by
  *    Householder QR in FP64 (A[k] <- Q, centre <- R) or, when D_k equals its row count, as
  *    A[k] <- identity, centre <- Theta'; the one-qubit gates are applied as each site is
  *    reached and the last centre is scaled to unit norm.
  *  MPS_EXACT_SVD: the canonical sweep + Jacobi SVD ladder, as for every other layer.
- * Layers with any truncating bond, the H-R_Y brickwork program and slots wider than 16 keep the
- * canonical sweep; under MPS_EXACT_MPO and MPS_EXACT_QR their ladder still splits each bond
+ * Layers with any truncating bond and slots wider than 16 keep the canonical sweep; under MPS_EXACT_MPO and MPS_EXACT_QR their ladder still splits each bond
  * that keeps all min(rows, cols) singular values exactly (identity or QR, centre renormalised
  * by |Theta'|) and runs the Jacobi SVD only where weight can be discarded.  Process-wide
  * setting, read at each launch.  Returns MPS_ERR_INVALID_ARG for another mode.

@@ -976,19 +976,30 @@ __device__ __forceinline__ cd gated_at(const At& at, const Gate2& g, int a, int 
 
 __device__ __forceinline__ bool finite_c(cd v) { return isfinite(v.re) && isfinite(v.im); }
 
+// The bit a site passes to its right bond.  Ladder: its output y.  The paper's brickwork layer
+// (§II-B, Eq. (2); CNOTs on the even bonds, then on the odd ones), written the same way with
+// one bit per bond: an odd site k is the target of CNOT(k-1, k) and the control of
+// CNOT(k, k+1), so it outputs y = x XOR p and passes y; an even site is the control of
+// CNOT(k, k+1) (passing its input x) and then the target of CNOT(k-1, k), so it outputs
+// y = x XOR p and passes x = y XOR p.  The gates U_k are applied first in both programs.
+__device__ __forceinline__ int mpo_bit(int k, int y, int p, bool brick) {
+  return (brick && !(k & 1)) ? (y ^ p) : y;
+}
+
 // A site between the reduced ends: A[k] <- B[k] (bonds 2 Dp x 2 x 2 Do), written to `slot` by
 // `nthreads` lanes; the old tensor is read through `at` from a staged copy, so the slot may be
 // overwritten.  Returns true if a value is not finite.
 template <int S, typename T, typename At>
 __device__ __forceinline__ bool mpo_plain_site(const At& at, const Gate2& g, int Dp, int Do, T* slot,
-                                               int lane, int nthreads) {
+                                               int lane, int nthreads, int k = 1,
+                                               bool brick = false) {
   bool bad = false;
   const int R = 2 * Do;
   const FastDiv fr(R), fdp(Dp), fdo(Do);
   for (int idx = lane; idx < 4 * Dp * R; idx += nthreads) {
     const int row = fr.q(idx), m = fr.r(idx), i = row >> 1, y = row & 1;
     const int p = fdp.q(i), a = fdp.r(i), q = fdo.q(m), b = fdo.r(m);
-    const cd v = (q == y) ? gated_at(at, g, a, y ^ p, b) : cd{0.0, 0.0};
+    const cd v = (q == mpo_bit(k, y, p, brick)) ? gated_at(at, g, a, y ^ p, b) : cd{0.0, 0.0};
     bad |= !finite_c(v);
     store_c<T, double>(slot, (size_t)row * S + m, v);
   }
@@ -1019,7 +1030,8 @@ __device__ __forceinline__ MpoBufs<T> mpo_bufs(LayerShared<S, T>& sh) {
 template <int S, typename T, typename Before, typename After>
 __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, After dnew,
                          const MpoPlan& plan, const double* theta, const double* phi,
-                         SitePrefetch<S, T>& pf, int part) {
+                         SitePrefetch<S, T>& pf, int part, int gmode = kGateRyRz,
+                         const double* pix = nullptr, bool brick = false) {
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
   constexpr int CS = 2 * S;  // row stride of the left carry (columns <= 2 S)
   constexpr int SP = LayerShared<S, T>::SP;
@@ -1053,7 +1065,7 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
   }
   bool bad = false;
   pf.load(st + (size_t)site_at(0) * SLOT, dold(site_at(0) - 1), dold(site_at(0)));
-  Gate2 gnext = site_gate(kGateRyRz, site_at(0), theta, phi, nullptr);
+  Gate2 gnext = site_gate(gmode, site_at(0), theta, phi, pix);
   for (int t = 0; t < total; ++t) {
     const int k = site_at(t);
     pf.commit(tb);
@@ -1063,12 +1075,12 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
       // the next site's load and gate overlap this step
       const int kn = site_at(t + 1);
       pf.load(st + (size_t)kn * SLOT, dold(kn - 1), dold(kn));
-      gnext = site_gate(kGateRyRz, kn, theta, phi, nullptr);
+      gnext = site_gate(gmode, kn, theta, phi, pix);
     }
     const int Dp = dold(k - 1), Do = dold(k), L = lm(k);
     const FastDiv fdp(Dp), fdo(Do);
     if (t < nl) {
-      // C_k[2a+s][(q,b)] = delta(q,s) sum_i C_{k-1}[a][i] B[k][i, s, (s,b)]
+      // C_k[2a+s][(q,b)] = sum_i C_{k-1}[a][i] B[k][i, s, (q,b)]
       const int rows = dnew(k - 1), R = 2 * Do;
       const FastDiv fr(R);
       const cd* C = cbuf(cur);
@@ -1077,13 +1089,15 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
         const int row = fr.q(idx), m = fr.r(idx), a = row >> 1, s_ = row & 1;
         const int q = fdo.q(m), b = fdo.r(m);
         cd acc{0.0, 0.0};
-        if (q == s_)
-          for (int i = 0; i < L; ++i) cfma(acc, C[a * CS + i], gated_at(at, g, fdp.r(i), s_ ^ fdp.q(i), b));
+        for (int i = 0; i < L; ++i) {
+          const int p = fdp.q(i);
+          if (q == mpo_bit(k, s_, p, brick)) cfma(acc, C[a * CS + i], gated_at(at, g, fdp.r(i), s_ ^ p, b));
+        }
         Cn[row * CS + m] = acc;
       }
       cur ^= 1;
     } else if (t < nl + nr) {
-      // R_k[i][s D_k + b] = sum_b' B[k][i, s, (s,b')] R_{k+1}[(s,b')][b]
+      // R_k[i][s D_k + b] = sum_b' B[k][i, s, (q,b')] R_{k+1}[(q,b')][b], q = the site's bit
       const int Dn = dnew(k), cols = 2 * Dn;
       const FastDiv fc(cols), fdn(Dn);
       const cd* Rk = rbuf(rcur);
@@ -1092,8 +1106,9 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
         const int i = fc.q(idx), f = fc.r(idx), s_ = fdn.q(f), b = fdn.r(f);
         const int p = fdp.q(i), a = fdp.r(i);
         cd acc{0.0, 0.0};
+        const int q = mpo_bit(k, s_, p, brick);
         for (int bp = 0; bp < Do; ++bp) {
-          const int mrow = (k == n - 1) ? bp : s_ * Do + bp;
+          const int mrow = (k == n - 1) ? bp : q * Do + bp;
           cfma(acc, gated_at(at, g, a, s_ ^ p, bp), Rk[mrow * S + b]);
         }
         Rn[i * S + f] = acc;
@@ -1104,11 +1119,21 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
       const bool lc = do_left && k == kl + 1, rc = do_right && k == kr;
       const cd* C = cbuf(cur);
       const cd* Rc = rbuf(rcur);
-      cd* V = cbuf(cur ^ 1);  // the free left-carry buffer: [D_kl][2][D_k^old]
-      const int rows = lc ? dnew(kl) : L;
-      if (lc) {
-        // V[a'][y][b'] = sum_i C[a'][i] (U A)[a(i), y XOR p(i), b']
-        const FastDiv f2o(2 * Do);
+      T* slot = st + (size_t)k * SLOT;
+      const int R = (k == n - 1) ? 1 : 2 * Do;
+      // B[k][i, y, m], zero off its bit's delta
+      auto bel = [&](int i, int y, int m) -> cd {
+        const int p = fdp.q(i), a = fdp.r(i);
+        if (k == n - 1) return gated_at(at, g, a, y ^ p, m);
+        return fdo.q(m) == mpo_bit(k, y, p, brick) ? gated_at(at, g, a, y ^ p, fdo.r(m))
+                                                    : cd{0.0, 0.0};
+      };
+      if (lc && rc) {
+        // both carries land here (short chains of the ladder): V = C B[k] in the free left
+        // buffer ([D_kl][2][D_k^old]; its bit is y), then V R
+        cd* V = cbuf(cur ^ 1);
+        const int rows = dnew(kl), cols = dnew(kr);
+        const FastDiv f2o(2 * Do), fc(cols);
         for (int idx = tid; idx < rows * 2 * Do; idx += kLayerThreads) {
           const int an = f2o.q(idx), r2 = f2o.r(idx), y = fdo.q(r2), bp = fdo.r(r2);
           cd acc{0.0, 0.0};
@@ -1116,34 +1141,40 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
           V[idx] = acc;
         }
         __syncthreads();
-      }
-      // left factor of row (r, y) at b': V (carried) or (U A)[a, y XOR p, b'] (plain)
-      auto left = [&](int r, int y, int bp) -> cd {
-        return lc ? V[(r * 2 + y) * Do + bp] : gated_at(at, g, fdp.r(r), y ^ fdp.q(r), bp);
-      };
-      T* slot = st + (size_t)k * SLOT;
-      if (rc) {
-        const int cols = dnew(kr);
-        const FastDiv fc(cols);
         for (int idx = tid; idx < rows * 2 * cols; idx += kLayerThreads) {
           const int row = fc.q(idx), j = fc.r(idx), r = row >> 1, y = row & 1;
           cd acc{0.0, 0.0};
           for (int bp = 0; bp < Do; ++bp) {
             const int mrow = (k == n - 1) ? bp : y * Do + bp;
-            cfma(acc, left(r, y, bp), Rc[mrow * S + j]);
+            cfma(acc, V[(r * 2 + y) * Do + bp], Rc[mrow * S + j]);
           }
           bad |= !finite_c(acc);
           store_c<T, double>(slot, (size_t)row * S + j, acc);
         }
-      } else {
-        const int R = (k == n - 1) ? 1 : 2 * Do;
+      } else if (lc) {
+        const int rows = dnew(kl);
         const FastDiv fr(R);
         for (int idx = tid; idx < rows * 2 * R; idx += kLayerThreads) {
           const int row = fr.q(idx), m = fr.r(idx), r = row >> 1, y = row & 1;
-          const int q = fdo.q(m), b = fdo.r(m);
-          const cd v = (k == n - 1 || q == y) ? left(r, y, b) : cd{0.0, 0.0};
-          bad |= !finite_c(v);
-          store_c<T, double>(slot, (size_t)row * S + m, v);
+          cd acc{0.0, 0.0};
+          for (int i = 0; i < L; ++i) cfma(acc, C[r * CS + i], bel(i, y, m));
+          bad |= !finite_c(acc);
+          store_c<T, double>(slot, (size_t)row * S + m, acc);
+        }
+      } else {
+        // rows are B's left index i = (p, a)
+        const int cols = dnew(kr);
+        const FastDiv fc(cols);
+        for (int idx = tid; idx < L * 2 * cols; idx += kLayerThreads) {
+          const int row = fc.q(idx), j = fc.r(idx), i = row >> 1, y = row & 1;
+          const int p = fdp.q(i), a = fdp.r(i), q = mpo_bit(k, y, p, brick);
+          cd acc{0.0, 0.0};
+          for (int bp = 0; bp < Do; ++bp) {
+            const int mrow = (k == n - 1) ? bp : q * Do + bp;
+            cfma(acc, gated_at(at, g, a, y ^ p, bp), Rc[mrow * S + j]);
+          }
+          bad |= !finite_c(acc);
+          store_c<T, double>(slot, (size_t)row * S + j, acc);
         }
       }
     }
@@ -1254,8 +1285,10 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
 template <int S, typename T>
 __global__ __launch_bounds__(kLayerThreads) void k_mpo_ends(T* state, int n, int chi, int layer,
                                                             MpoPlan plan, const double* theta,
-                                                            const double* phi, double* trunc_err,
-                                                            int* status, int batch) {
+                                                            const double* phi,
+                                                            const double* pixels, int brick,
+                                                            double* trunc_err, int* status,
+                                                            int batch) {
   __shared__ LayerShared<S, T> sh;
   const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
   const int b = kXcds * (j >> 1) + xcd, part = j & 1;
@@ -1266,15 +1299,17 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_ends(T* state, int n, int
     for (int k = threadIdx.x; k < n - 1; k += kLayerThreads) trunc_err[(size_t)b * (n - 1) + k] = 0.0;
   SitePrefetch<S, T> pf;
   const bool bad = mpo_ends<S, T>(mpo_bufs(sh), state + (size_t)b * n * ((size_t)2 * S * S * 2), n, dold,
-                                  dnew, plan, theta, phi, pf, part);
+                                  dnew, plan, theta, phi, pf, part, brick ? kGateHRy : kGateRyRz,
+                                  pixels ? pixels + (size_t)b * n : nullptr, brick != 0);
   if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
 }
 
 template <int S, typename T>
 __global__ __launch_bounds__(kLayerThreads) void k_mpo_sites(T* state, int n, int chi, int layer,
                                                              MpoPlan plan, const double* theta,
-                                                             const double* phi, int* status,
-                                                             int batch) {
+                                                             const double* phi,
+                                                             const double* pixels, int brick,
+                                                             int* status, int batch) {
   // a site between the ends has old bonds D^old = D / 2 <= S / 2
   constexpr int H = S / 2 > 0 ? S / 2 : 1;
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
@@ -1292,8 +1327,10 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_sites(T* state, int n, in
   }
   __syncthreads();
   auto at = [&](int a, int s_, int c) { return to_cd(old[(a * 2 + s_) * Do + c]); };
-  const bool bad = mpo_plain_site<S, T>(at, site_gate(kGateRyRz, k, theta, phi, nullptr), Dp, Do,
-                                        slot, threadIdx.x, kLayerThreads);
+  const Gate2 g = site_gate(brick ? kGateHRy : kGateRyRz, k, theta, phi,
+                            pixels ? pixels + (size_t)b * n : nullptr);
+  const bool bad = mpo_plain_site<S, T>(at, g, Dp, Do, slot, threadIdx.x, kLayerThreads, k,
+                                        brick != 0);
   if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
 }
 
@@ -1447,19 +1484,24 @@ hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, i
                         double* trunc_err, int* status, hipStream_t stream) {
   const dim3 grid(batch), block(kLayerThreads);
   MpoPlan plan;
-  if (program == kLayerRyRzLadder && g_exact_qr == kExactMpo && layer_keeps_all(n, chi, layer) &&
+  // the brickwork program takes the site-local form when its two end carries land on two
+  // different sites (its even-site bit rule is not in the meeting-carries step)
+  if (g_exact_qr == kExactMpo && layer_keeps_all(n, chi, layer) &&
       mpo_plan(n, [&](int k) { return bond_dim(n, chi, layer, k); },
-               [&](int k) { return bond_dim(n, chi, layer + 1, k); }, plan)) {
+               [&](int k) { return bond_dim(n, chi, layer + 1, k); }, plan) &&
+      (program == kLayerRyRzLadder || (program == kLayerHRyBrickwork && plan.kl + 1 < plan.kr))) {
+    const int brick = program == kLayerHRyBrickwork;
     const unsigned groups = (unsigned)((batch + kXcds - 1) / kXcds);
     const int nmid = plan.kr - plan.kl - 2;
     switch (S) {
 #define ANOMPS_KM(SV)                                                                              \
   case SV:                                                                                         \
     hipLaunchKernelGGL((k_mpo_ends<SV, T>), dim3(kXcds * groups * 2), block, 0, stream, state, n,  \
-                       chi, layer, plan, theta, phi, trunc_err, status, batch);                    \
+                       chi, layer, plan, theta, phi, pixels, brick, trunc_err, status, batch);     \
     if (nmid > 0)                                                                                  \
       hipLaunchKernelGGL((k_mpo_sites<SV, T>), dim3(kXcds * groups * (unsigned)nmid), block, 0,    \
-                         stream, state, n, chi, layer, plan, theta, phi, status, batch);           \
+                         stream, state, n, chi, layer, plan, theta, phi, pixels, brick, status,    \
+                         batch);                                                                   \
     break;
       ANOMPS_KM(2) ANOMPS_KM(4) ANOMPS_KM(8) ANOMPS_KM(16)
 #undef ANOMPS_KM
