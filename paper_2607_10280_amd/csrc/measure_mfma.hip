@@ -213,19 +213,69 @@ __device__ __forceinline__ void conj4(const C (&a)[4], C (&b)[4]) {
 // Left transfer E' = sum_u A_u^T E conj(A_u) with E given as its A-operand (row form):
 // X_u = E conj(A_u), then E'^T = sum_u X_u^T A_u (the accumulator of X_u is the A-operand of
 // X_u^T).  a = column forms of A_0, A_1.  Returns E'^T.
+// Gauss's three partial products of a sum of complex products, kept apart until the sum is
+// complete: t1 = sum Ar Br, t2 = sum Ai Bi, t3 = sum (Ar + Ai)(Br +- Bi).  For B (sign +):
+// re = t1 - t2, im = t3 - t1 - t2; for conj(B) (sign -): re = t1 + t2, im = t3 - t1 + t2.  The
+// conjugate never has to be formed, and several products into one output are combined once.
+struct Gauss3 {
+  f4 t1, t2, t3;
+};
+__device__ __forceinline__ Gauss3 gauss_zero() {
+  const f4 z = f4{0.f, 0.f, 0.f, 0.f};
+  return Gauss3{z, z, z};
+}
+// bs[kc] = Br + Bi (or Br - Bi for conj(B)), computed once per B operand.
+__device__ __forceinline__ void gauss_acc(Gauss3& g, const cx<float> (&a)[4], const cx<float> (&b)[4],
+                                          const float (&bs)[4]) {
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    g.t1 = mfma(a[kc].re, b[kc].re, g.t1);
+    g.t2 = mfma(a[kc].im, b[kc].im, g.t2);
+    g.t3 = mfma(a[kc].re + a[kc].im, bs[kc], g.t3);
+  }
+}
+template <bool CONJ>
+__device__ __forceinline__ Acc<kMmaGauss> gauss_done(const Gauss3& g) {
+  Acc<kMmaGauss> c;
+  c.re = CONJ ? g.t1 + g.t2 : g.t1 - g.t2;
+  c.im = CONJ ? g.t3 - g.t1 + g.t2 : g.t3 - g.t1 - g.t2;
+  return c;
+}
+
 template <int MODE, typename C>
 __device__ __forceinline__ Acc<MODE> left_transfer_t(const C (&e)[4], const C (&a)[2][4]) {
-  Acc<MODE> out = acc_zero<MODE>();
+  if constexpr (MODE == kMmaGauss) {
+    float bsum[2][4], bdif[2][4];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    C ac[4], xa[4];
-    conj4(a[u], ac);
-    Acc<MODE> x = acc_zero<MODE>();
-    cgemm<MODE>(x, e, ac);
-    acc_as_b(x, xa);
-    cgemm<MODE>(out, xa, a[u]);
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        bsum[u][kc] = a[u][kc].re + a[u][kc].im;
+        bdif[u][kc] = a[u][kc].re - a[u][kc].im;
+      }
+    Gauss3 go = gauss_zero();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      Gauss3 gx = gauss_zero();
+      gauss_acc(gx, e, a[u], bdif[u]);  // X_u = E conj(A_u)
+      C xa[4];
+      acc_as_b(gauss_done<true>(gx), xa);
+      gauss_acc(go, xa, a[u], bsum[u]);  // + X_u^T A_u
+    }
+    return gauss_done<false>(go);
+  } else {
+    Acc<MODE> out = acc_zero<MODE>();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      C ac[4], xa[4];
+      conj4(a[u], ac);
+      Acc<MODE> x = acc_zero<MODE>();
+      cgemm<MODE>(x, e, ac);
+      acc_as_b(x, xa);
+      cgemm<MODE>(out, xa, a[u]);
+    }
+    return out;
   }
-  return out;
 }
 
 }  // namespace
@@ -266,23 +316,10 @@ __device__ __forceinline__ void env16_image(const typename MmaReal<MODE>::type* 
     if (t + 1 < n) fetch(t + 1, nxt);
     C eo[4];
     acc_as_b(e, eo);
-    if (!right) {
-      // L_{k+1} = sum_u A_u^T L_k conj(A_u)
-      e = left_transfer_t<MODE>(eo, cur.a);
-    } else {
-      // R_k = sum_s A_s R_{k+1} A_s^H: Y_s = R A_s^H, R_k^T = sum_s Y_s^T A_s^T (row forms)
-      Acc<MODE> o = acc_zero<MODE>();
-#pragma unroll
-      for (int s_ = 0; s_ < 2; ++s_) {
-        C ah[4], ya[4];
-        conj4(cur.a[s_], ah);
-        Acc<MODE> y = acc_zero<MODE>();
-        cgemm<MODE>(y, eo, ah);
-        acc_as_b(y, ya);
-        cgemm<MODE>(o, ya, cur.a[s_]);
-      }
-      e = o;
-    }
+    // Left: L_{k+1} = sum_u A_u^T L_k conj(A_u) from the column forms.  Right:
+    // R_k = sum_s A_s R_{k+1} A_s^H, i.e. Y_s = R conj(A_s^T) and R_k^T = sum_s Y_s^T A_s^T: the
+    // same two products with the row forms (the row form of A_s is the column form of A_s^T).
+    e = left_transfer_t<MODE>(eo, cur.a);
     store_env(right ? n - 1 - t : t + 1);
     cur = nxt;
   }
