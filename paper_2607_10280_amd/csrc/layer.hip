@@ -976,6 +976,15 @@ __device__ __forceinline__ cd gated_at(const At& at, const Gate2& g, int a, int 
 
 __device__ __forceinline__ bool finite_c(cd v) { return isfinite(v.re) && isfinite(v.im); }
 
+// Orders LDS accesses across the lanes of a one-wavefront workgroup: waits for the wave's own
+// LDS operations and keeps the compiler from moving memory accesses across, but leaves its
+// global loads in flight (a __syncthreads fences global memory too, i.e. waits for every
+// outstanding load and store, which would undo the prefetches below).
+__device__ __forceinline__ void lds_sync() {
+  static_assert(kLayerThreads == 64, "one wavefront per workgroup");
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 // The bit a site passes to its right bond.  Ladder: its output y.  The paper's brickwork layer
 // (§II-B, Eq. (2); CNOTs on the even bonds, then on the odd ones), written the same way with
 // one bit per bond: an odd site k is the target of CNOT(k-1, k) and the control of
@@ -1031,7 +1040,8 @@ template <int S, typename T, typename Before, typename After>
 __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, After dnew,
                          const MpoPlan& plan, const double* theta, const double* phi,
                          SitePrefetch<S, T>& pf, int part, int gmode = kGateRyRz,
-                         const double* pix = nullptr, bool brick = false) {
+                         const double* pix = nullptr, bool brick = false, int extra_lo = 0,
+                         int extra_hi = -1) {
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
   constexpr int CS = 2 * S;  // row stride of the left carry (columns <= 2 S)
   constexpr int SP = LayerShared<S, T>::SP;
@@ -1043,13 +1053,16 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
   auto lm = [&](int k) { return k == 0 ? 1 : 2 * dold(k - 1); };
   cx<T>* tb = bufs.tb;
   auto at = [&](int a, int s_, int b) { return to_cd(tb[(a * 2 + s_) * SP + b]); };
-  // Visiting order: left chain 0..kl, right chain n-1..kr+1, then the carry sites.
+  // Visiting order: left chain 0..kl, right chain n-1..kr+1, the carry sites, then the plain
+  // sites extra_lo..extra_hi (sites between the ends that the caller hands to this part).
   const int nl = do_left ? kl + 1 : 0, nr = do_right ? n - 1 - kr : 0;
   const bool two = do_left && do_right && !meet;
-  const int total = nl + nr + (two ? 2 : 1);
+  const int ncarry = nl + nr + (two ? 2 : 1);
+  const int total = ncarry + (extra_hi >= extra_lo ? extra_hi - extra_lo + 1 : 0);
   auto site_at = [&](int t) {
     if (t < nl) return t;
     if (t < nl + nr) return n - 1 - (t - nl);
+    if (t >= ncarry) return extra_lo + (t - ncarry);
     return (t == nl + nr && do_left) ? kl + 1 : kr;
   };
   cd* const c0 = bufs.c[0];
@@ -1064,19 +1077,23 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
     if (do_right) r0[0] = cd{1.0, 0.0};
   }
   bool bad = false;
+  // Sites are loaded two steps ahead (pf: the next step's site, pf2: the one after), and the next
+  // site's gate is computed while this step runs: each step is short next to a load's latency.
+  SitePrefetch<S, T> pf2;
   pf.load(st + (size_t)site_at(0) * SLOT, dold(site_at(0) - 1), dold(site_at(0)));
+  if (total > 1) pf2.load(st + (size_t)site_at(1) * SLOT, dold(site_at(1) - 1), dold(site_at(1)));
   Gate2 gnext = site_gate(gmode, site_at(0), theta, phi, pix);
   for (int t = 0; t < total; ++t) {
     const int k = site_at(t);
     pf.commit(tb);
-    __syncthreads();
+    lds_sync();
     const Gate2 g = gnext;
-    if (t + 1 < total) {
-      // the next site's load and gate overlap this step
-      const int kn = site_at(t + 1);
-      pf.load(st + (size_t)kn * SLOT, dold(kn - 1), dold(kn));
-      gnext = site_gate(gmode, kn, theta, phi, pix);
+    pf = pf2;
+    if (t + 2 < total) {
+      const int kn = site_at(t + 2);
+      pf2.load(st + (size_t)kn * SLOT, dold(kn - 1), dold(kn));
     }
+    if (t + 1 < total) gnext = site_gate(gmode, site_at(t + 1), theta, phi, pix);
     const int Dp = dold(k - 1), Do = dold(k), L = lm(k);
     const FastDiv fdp(Dp), fdo(Do);
     if (t < nl) {
@@ -1114,6 +1131,9 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
         Rn[i * S + f] = acc;
       }
       rcur ^= 1;
+    } else if (t >= ncarry) {
+      bad |= mpo_plain_site<S, T>(at, g, Dp, Do, st + (size_t)k * SLOT, tid, kLayerThreads, k,
+                                  brick);
     } else {
       // a carry site: C B[k] when k = kl+1 (left end), B[k] R when k = kr (right end)
       const bool lc = do_left && k == kl + 1, rc = do_right && k == kr;
@@ -1140,7 +1160,7 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
           for (int i = 0; i < L; ++i) cfma(acc, C[an * CS + i], gated_at(at, g, fdp.r(i), y ^ fdp.q(i), bp));
           V[idx] = acc;
         }
-        __syncthreads();
+        lds_sync();
         for (int idx = tid; idx < rows * 2 * cols; idx += kLayerThreads) {
           const int row = fc.q(idx), j = fc.r(idx), r = row >> 1, y = row & 1;
           cd acc{0.0, 0.0};
@@ -1178,7 +1198,7 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
         }
       }
     }
-    __syncthreads();
+    lds_sync();
   }
   // identity tensors of the reduced sites
   for (int k = 0; k < nl; ++k) {
@@ -1216,11 +1236,11 @@ __device__ int mpo_layer(LayerShared<S, T>& sh, T* st, int n, Before dold, After
   if (k0 <= k1) pf.load(st + (size_t)k0 * SLOT, dold(k0 - 1), dold(k0));
   for (int k = k0; k <= k1; ++k) {
     pf.commit(sh.tb);
-    __syncthreads();
+    lds_sync();
     if (k + 1 <= k1) pf.load(st + (size_t)(k + 1) * SLOT, dold(k), dold(k + 1));
     bad |= mpo_plain_site<S, T>(at, site_gate(kGateRyRz, k, theta, phi, nullptr), dold(k - 1),
                                 dold(k), st + (size_t)k * SLOT, tid, kLayerThreads);
-    __syncthreads();
+    lds_sync();
   }
   return __any(bad) ? kImgNonfinite : 0;
 }
@@ -1325,7 +1345,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_sites(T* state, int n, in
     const int row = fdo.q(idx), c = fdo.r(idx);
     old[idx] = cx<T>{slot[2 * ((size_t)row * S + c)], slot[2 * ((size_t)row * S + c) + 1]};
   }
-  __syncthreads();
+  lds_sync();
   auto at = [&](int a, int s_, int c) { return to_cd(old[(a * 2 + s_) * Do + c]); };
   const Gate2 g = site_gate(brick ? kGateHRy : kGateRyRz, k, theta, phi,
                             pixels ? pixels + (size_t)b * n : nullptr);
@@ -1535,6 +1555,7 @@ constexpr int kMaxRun = 16;
 
 struct MpoRun {
   int layer0, count, core_lo, core_hi;
+  int carry_elems;  // complex128 elements of one carry buffer (the larger end's need)
   MpoPlan plan[kMaxRun];
 };
 
@@ -1545,20 +1566,26 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_run_ends(T* state, int n,
                                                                 double* trunc_err, int* status,
                                                                 int batch) {
   // One end per workgroup (a run never has the two carries meeting in one site), so the carry
-  // LDS holds one ping-pong pair: ~21 KiB at S = 16 instead of the layer kernel's ~39 KiB.
+  // LDS holds one ping-pong pair, sized on the host for this run's bond dimensions (8 KiB at
+  // 7x7, L = 4, chi = 16, against 16 KiB for the slot's worst case): all of a batch's end
+  // workgroups then fit on the chip at once.
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
   constexpr int SP = LayerShared<S, T>::SP;
-  __shared__ cd pool[2 * 2 * S * S];
-  __shared__ cx<T> tbuf[2 * S * SP];
+  extern __shared__ cd dyn_lds[];
+  cd* pool = dyn_lds;
+  cx<T>* tbuf = reinterpret_cast<cx<T>*>(pool + 2 * run.carry_elems);
   const int w = blockIdx.x, xcd = w % kXcds, j = w / kXcds;
   const int b = kXcds * (j >> 1) + xcd, part = j & 1;
   if (b >= batch) return;
+  // This chain of short dependent steps runs beside the core launch and bounds the call: its
+  // waves take issue priority over the core's on a shared SIMD.
+  __builtin_amdgcn_s_setprio(2);
   const int tid = threadIdx.x;
   T* st = state + (size_t)b * n * SLOT;
   SitePrefetch<S, T> pf;
   const MpoBufs<T> bufs =
-      part == 0 ? MpoBufs<T>{{pool, pool + 2 * S * S}, {nullptr, nullptr}, tbuf}
-                : MpoBufs<T>{{nullptr, nullptr}, {pool, pool + 2 * S * S}, tbuf};
+      part == 0 ? MpoBufs<T>{{pool, pool + run.carry_elems}, {nullptr, nullptr}, tbuf}
+                : MpoBufs<T>{{nullptr, nullptr}, {pool, pool + run.carry_elems}, tbuf};
   auto at = [&](int a, int s_, int c) { return to_cd(tbuf[(a * 2 + s_) * SP + c]); };
   bool bad = false;
   for (int r = 0; r < run.count; ++r) {
@@ -1571,27 +1598,11 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_run_ends(T* state, int n,
       for (int k = tid; k < n - 1; k += kLayerThreads)
         trunc_err[((size_t)r * batch + b) * (n - 1) + k] = 0.0;
     const MpoPlan plan = run.plan[r];
-    bad |= mpo_ends<S, T>(bufs, st, n, dold, dnew, plan, th, ph, pf, part);
-    // this layer's sites between its own ends and the core, on this side
+    // with this layer's sites between its own ends and the core, on this side
     const int k0 = part == 0 ? plan.kl + 2 : run.core_hi + 1;
     const int k1 = part == 0 ? run.core_lo - 1 : plan.kr - 1;
-    Gate2 gnext{};
-    if (k0 <= k1) {
-      pf.load(st + (size_t)k0 * SLOT, dold(k0 - 1), dold(k0));
-      gnext = site_gate(kGateRyRz, k0, th, ph, nullptr);
-    }
-    for (int k = k0; k <= k1; ++k) {
-      pf.commit(tbuf);
-      __syncthreads();
-      const Gate2 g = gnext;
-      if (k + 1 <= k1) {
-        pf.load(st + (size_t)(k + 1) * SLOT, dold(k), dold(k + 1));
-        gnext = site_gate(kGateRyRz, k + 1, th, ph, nullptr);
-      }
-      bad |= mpo_plain_site<S, T>(at, g, dold(k - 1), dold(k), st + (size_t)k * SLOT, tid,
-                                  kLayerThreads);
-      __syncthreads();
-    }
+    bad |= mpo_ends<S, T>(bufs, st, n, dold, dnew, plan, th, ph, pf, part, kGateRyRz, nullptr,
+                          false, k0, k1);
     // the next layer reads what this one stored: the barrier's fence makes it visible
     __syncthreads();
   }
@@ -1624,7 +1635,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_run_core(T* state, int n,
       buf[0][idx] = to_cd(cx<T>{slot[2 * ((size_t)row * S + c)], slot[2 * ((size_t)row * S + c) + 1]});
     }
   }
-  __syncthreads();
+  lds_sync();
   int cur = 0;
   bool bad = false;
   for (int r = 0; r < run.count; ++r) {
@@ -1643,7 +1654,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_run_core(T* state, int n,
         const int p = fdp.q(i), a = fdp.r(i), q = fdo.q(m), c = fdo.r(m);
         dst[idx] = (q == y) ? gated_at(at, g, a, y ^ p, c) : cd{0.0, 0.0};
       }
-      __syncthreads();
+      lds_sync();
       cur ^= 1;
       Dp *= 2;
       Do *= 2;
@@ -1676,6 +1687,17 @@ int mpo_run(int n, int chi, int S, int layer, int max_count, MpoRun& run) {
     ++count;
   }
   run.count = count;
+  // One carry buffer: the left carry C_k (D_k rows, row stride 2S), the carry site's product
+  // (D_kl x 2 x D_{kl+1}^old) and the right carry R_k (2 D_{k-1}^old rows, row stride S).
+  int need = 1;
+  for (int r = 0; r < count; ++r) {
+    const int l = layer + r, kl = run.plan[r].kl, kr = run.plan[r].kr;
+    const int dl = bond_dim(n, chi, l + 1, kl);
+    need = std::max(need, dl * 2 * S);
+    need = std::max(need, dl * 2 * bond_dim(n, chi, l, kl + 1));
+    if (kr <= n - 2) need = std::max(need, 2 * bond_dim(n, chi, l, kr) * S);
+  }
+  run.carry_elems = (need + 15) & ~15;
   return count;
 }
 
@@ -1722,8 +1744,10 @@ hipError_t launch_mpo_run(T* state, int n, int chi, int S, const MpoRun& run, in
   switch (S) {
 #define ANOMPS_KR(SV)                                                                              \
   case SV:                                                                                         \
-    hipLaunchKernelGGL((k_mpo_run_ends<SV, T>), dim3(kXcds * groups * 2), block, 0, sd->stream,    \
-                       state, n, chi, run, theta, phi, trunc_err, status, batch);                  \
+    hipLaunchKernelGGL((k_mpo_run_ends<SV, T>), dim3(kXcds * groups * 2), block,                   \
+                       (unsigned)(2 * run.carry_elems * sizeof(cd) +                               \
+                                  2 * SV * LayerShared<SV, T>::SP * sizeof(cx<T>)),                \
+                       sd->stream, state, n, chi, run, theta, phi, trunc_err, status, batch);      \
     if ((e = hipGetLastError()) != hipSuccess) break;                                              \
     hipLaunchKernelGGL((k_mpo_run_core<SV, T>), dim3(kXcds * groups * ncore), block, 0, stream,    \
                        state, n, chi, run, theta, phi, status, batch);                             \
