@@ -16,7 +16,9 @@
  * Conventions shared by every call:
  *  - Ownership: every pointer argument is caller-owned.  Unless a parameter says "host", it
  *    points to DEVICE memory of the current HIP device.  The library never allocates device
- *    memory in these calls; it keeps only host-side tables and the message of the last error.
+ *    memory in these calls; it keeps only host-side tables, the message of the last error and,
+ *    per device, one stream of its own with two events (default priority, created by the first
+ *    mps_apply_layers call that runs a run of exact layers, kept until the process ends).
  *  - Streams: every call only enqueues work on `stream` (0 = the null stream) and returns
  *    without synchronising.  Independent batches may run on different streams.
  *  - Errors: argument and capacity errors are detected on the host and returned before any

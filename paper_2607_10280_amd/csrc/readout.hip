@@ -40,10 +40,52 @@ __global__ void k_coeffs(const R* A, const R* B, const R* D, int m, R* coeff) {
   coeff[gid] = (R)0.25 * acc;
 }
 
-// One workgroup per image: q[j] in LDS, then y[o] = sum_j W[o][j] q[j] + bias[o].
+// y[b][o] = sum_j W[o][j] q_b[j] + bias[o], q_b[j] = c_j0 + sum_alpha c_j,alpha <P_alpha>_bj.
+// One workgroup per (block of kRoOut outputs, block of kRoImg images): the block's rows of W
+// (contiguous in memory) and the images' q vectors are staged in LDS, so W is read once per
+// image block instead of once per image, and every global read is coalesced.  LDS rows are
+// padded to an odd stride so that lanes on consecutive rows fall on different banks.
+constexpr int kRoOut = 128, kRoImg = 16, kRoThreads = 256;
+constexpr size_t kRoLds = 64 * 1024;  // LDS budget of one block
+
+__host__ __device__ inline int ro_stride(int m) { return m | 1; }
+
 template <typename R>
-__global__ void k_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int m,
-                          int out_dim, R* y) {
+__global__ __launch_bounds__(kRoThreads) void k_readout(const R* pauli, const R* coeff, const R* W,
+                                                        const R* bias, int batch, int m,
+                                                        int out_dim, int ob, int ib, R* y) {
+  extern __shared__ unsigned char smem[];
+  const int mp = ro_stride(m);
+  R* ws = reinterpret_cast<R*>(smem);  // [ob][mp]
+  R* qs = ws + (size_t)ob * mp;         // [ib][mp]
+  const int o0 = blockIdx.x * ob, b0 = blockIdx.y * ib, tid = threadIdx.x;
+  const int no = min(ob, out_dim - o0), nb = min(ib, batch - b0);
+  for (int idx = tid; idx < no * m; idx += kRoThreads) {
+    const int oo = idx / m, jj = idx - oo * m;
+    ws[oo * mp + jj] = W[(size_t)o0 * m + idx];
+  }
+  for (int idx = tid; idx < nb * m; idx += kRoThreads) {
+    const int bi = idx / m, jj = idx - bi * m;
+    const R* pb = pauli + ((size_t)(b0 + bi) * m + jj) * 15;
+    R acc = coeff[jj * 16];
+    for (int al = 0; al < 15; ++al) acc += coeff[jj * 16 + al + 1] * pb[al];
+    qs[bi * mp + jj] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nb * no; idx += kRoThreads) {
+    const int bi = idx / no, oo = idx - bi * no;
+    R acc = bias ? bias[o0 + oo] : (R)0;
+    const R* wr = ws + oo * mp;
+    const R* qv = qs + bi * mp;
+    for (int jj = 0; jj < m; ++jj) acc += wr[jj] * qv[jj];
+    y[(size_t)(b0 + bi) * out_dim + o0 + oo] = acc;
+  }
+}
+
+// Feature vectors too long for two LDS rows of the blocked kernel: one workgroup per image.
+template <typename R>
+__global__ void k_readout_image(const R* pauli, const R* coeff, const R* W, const R* bias, int m,
+                                int out_dim, R* y) {
   extern __shared__ unsigned char smem[];
   R* qv = reinterpret_cast<R*>(smem);
   const int b = blockIdx.x;
@@ -75,8 +117,18 @@ template <typename R>
 hipError_t launch_readout(const R* pauli, const R* coeff, const R* W, const R* bias, int batch,
                           int m, int out_dim, R* y, hipStream_t stream) {
   if (batch == 0 || out_dim == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_readout<R>, dim3(batch), dim3(256), (size_t)m * sizeof(R), stream, pauli,
-                     coeff, W, bias, m, out_dim, y);
+  const size_t row = (size_t)ro_stride(m) * sizeof(R);
+  int ob = out_dim < kRoOut ? out_dim : kRoOut, ib = batch < kRoImg ? batch : kRoImg;
+  while ((size_t)(ob + ib) * row > kRoLds && ob > 1) ob = (ob + 1) / 2;
+  while ((size_t)(ob + ib) * row > kRoLds && ib > 1) ib = (ib + 1) / 2;
+  if ((size_t)(ob + ib) * row > kRoLds) {
+    hipLaunchKernelGGL(k_readout_image<R>, dim3(batch), dim3(256), (size_t)m * sizeof(R), stream,
+                       pauli, coeff, W, bias, m, out_dim, y);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)((out_dim + ob - 1) / ob), (unsigned)((batch + ib - 1) / ib));
+  hipLaunchKernelGGL(k_readout<R>, grid, dim3(kRoThreads), (size_t)(ob + ib) * row, stream, pauli,
+                     coeff, W, bias, batch, m, out_dim, ob, ib, y);
   return hipGetLastError();
 }
 

@@ -256,6 +256,30 @@ def test_readout(A, f64):
     assert np.abs(y.cpu().numpy() - ref_y).max() <= tol * 10
 
 
+@pytest.mark.parametrize("f64,B,m,out_dim", [(False, 37, 156, 784), (True, 37, 156, 784),
+                                             (True, 3, 4096, 40), (False, 19, 1, 5)])
+def test_readout_blocks(A, f64, B, m, out_dim):
+    """The blocked readout on ragged image and output blocks, a block size cut down to fit LDS
+    (156 observables in FP64), the one-image-per-workgroup form for very long feature vectors
+    (4096, the largest, in FP64) and a single observable, against the oracle's readout."""
+    import torch
+    rng = np.random.default_rng(700 + m)
+    pauli = rng.uniform(-1, 1, (B, m, 15))
+    a, bb, d, w, bias = inputs.readout_params(m, out_dim, 701)
+    dt = torch.float64 if f64 else torch.float32
+    T = lambda v: torch.as_tensor(v, dtype=dt, device="cuda").contiguous()
+    print(f"[case] readout f64={f64} B={B} m={m} out={out_dim}", flush=True)
+    coeff = torch.empty((m, 16), dtype=dt, device="cuda")
+    A.ano_coeffs(T(a), T(bb), T(d), coeff)
+    y = torch.empty((B, out_dim), dtype=dt, device="cuda")
+    pd = T(pauli)
+    A.ano_readout(pd, coeff, T(w), T(bias), y)
+    torch.cuda.synchronize()
+    ref_y = oread.readout(pd.cpu().numpy().astype(np.float64), a, bb, d, w, bias)
+    tol = 1e-11 if f64 else 2e-5
+    assert np.abs(y.cpu().numpy() - ref_y).max() <= tol * max(1.0, np.abs(ref_y).max())
+
+
 # ------------------------------------------------------------------ full-size workload
 def test_headline_size_sampled(A):
     """7x7, L=4, chi=16, batch 1024 (complex64 / FP64 SVD): sampled images against the exact
