@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--plain-images", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the eager step instead of its HIP-graph replay")
     ap.add_argument("--no-svd-compare", action="store_true",
                     help="skip the extra timing with every layer through the SVD ladder")
     ap.add_argument("--workload", default="headline",
@@ -537,7 +539,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # Eager: one stream-ordered call per step function.
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -545,10 +547,38 @@ def main():
         step()
     e1.record(stream)
     torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / args.steps
+    eager_out = out_d.cpu().numpy()
+    eager_y = y_d.cpu().numpy()
+
+    # The same step captured once as a HIP graph and replayed (no host launch gaps between the
+    # step's kernels; the library's second stream for layer runs joins the capture through its
+    # fork/join events).  Its outputs must equal the eager step's bit for bit.
+    graph = None
+    if not args.no_graph:
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=cs):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
+    e1.record(stream)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = e0.elapsed_time(e1) / args.steps
     status = batch.status.cpu().numpy()
     gpu_out = out_d.cpu().numpy()
+    graph_same = graph is None or (np.array_equal(gpu_out, eager_out)
+                                   and np.array_equal(y_d.cpu().numpy(), eager_y))
 
     # Per-call durations (HIP events on the launch stream), same steps again.
     per = {}
@@ -634,6 +664,10 @@ def main():
         "unit": "images/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "timing": {"mode": "eager" if graph is None else "hip_graph",
+                   "eager_ms_per_step": round(eager_ms, 4),
+                   "eager_images_per_s": round(B / (eager_ms * 1e-3), 1),
+                   "graph_identical_to_eager": bool(graph_same)},
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {anomps.PREC_FP32: "c64+f64svd", anomps.PREC_FP64: "f64",
                   anomps.PREC_SPLIT_BF16: "c64(split-bf16 mfma)+f64svd"}[prec],
