@@ -99,3 +99,49 @@ def test_run_argument_errors(A):
         A.apply_layers(b, th[:1], th[:1])  # nothing left
     torch.cuda.synchronize()
     assert int(b.status.cpu()[0]) == 0
+
+
+def test_run_inside_hip_graph(A):
+    """init + mps_apply_layers (a run, so the ends go to the library's second stream) + the
+    measurement captured as one HIP graph; three replays with eager work and synchronisations
+    between them each equal the eager result bit for bit."""
+    import torch
+    p, L, chi, B = 7, 4, 16, 64
+    n = p * p
+    x = inputs.blob_images(B, p, 630)
+    th, ph = inputs.layer_angles(L, n, 631)
+    pairs = inputs.neighbour_pairs(p)
+    print(f"[case] graph replay B={B} n={n} L={L} chi={chi}", flush=True)
+    dev = "cuda"
+    pix = torch.as_tensor(x, device=dev).contiguous()
+    thd = torch.as_tensor(th, device=dev).contiguous()
+    phd = torch.as_tensor(ph, device=dev).contiguous()
+    pd = torch.as_tensor(pairs, device=dev).contiguous()
+    b = A.new_batch(n, chi, L, B, A.PREC_FP32)
+    out = torch.empty((B, len(pairs), 15), dtype=torch.float32, device=dev)
+
+    def step():
+        A.init_batch(b, pix)
+        A.apply_layers(b, thd, phd)
+        A.pauli_pair_expect(b, pd, out)
+
+    step()
+    torch.cuda.synchronize()
+    eager = out.cpu().numpy().copy()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        step()
+    for r in range(3):
+        out.zero_()
+        step()                       # eager work between the replays
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager)
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {r}"
+    assert np.all(b.status.cpu().numpy() == 0)
