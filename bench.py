@@ -631,7 +631,7 @@ def main():
     exact = [l for l in range(L) if workload.layer_keeps_all(n, chi, l)]
 
     # Roofline of the dominant kernel family.
-    lay_flops = sum(workload.layer_flops(n, chi, l)["total_fp64"] for l in range(L)) * B
+    lay_flops = sum(workload.layer_flops(n, chi, l, n_layers=L)["total_fp64"] for l in range(L)) * B
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
     mfma = prec == anomps.PREC_FP32 and anomps.slot_dim(n, chi, L) == 16
     cand = {

@@ -190,17 +190,19 @@ int mps_apply_layer_program(mps_batch* b, int32_t program, const double* theta,
     if (b->precision == MPS_PREC_FP64)
       e = launch_layer_wide<double>((double*)b->state, wide_ws(b, S), b->n_sites, b->chi, S,
                                     b->layers_done, b->batch, program, theta, phi, pixels,
-                                    trunc_err, b->status, stream);
+                                    trunc_err, b->status, b->n_layers, stream);
     else
       e = launch_layer_wide<float>((float*)b->state, wide_ws(b, S), b->n_sites, b->chi, S,
                                    b->layers_done, b->batch, program, theta, phi, pixels,
-                                   trunc_err, b->status, stream);
+                                   trunc_err, b->status, b->n_layers, stream);
   } else if (b->precision == MPS_PREC_FP64) {
     e = launch_layer<double>((double*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
-                             program, theta, phi, pixels, trunc_err, b->status, stream);
+                             program, theta, phi, pixels, trunc_err, b->status, b->n_layers,
+                             stream);
   } else {
     e = launch_layer<float>((float*)b->state, b->n_sites, b->chi, S, b->layers_done, b->batch,
-                            program, theta, phi, pixels, trunc_err, b->status, stream);
+                            program, theta, phi, pixels, trunc_err, b->status, b->n_layers,
+                            stream);
   }
   if (e != hipSuccess) return check_hip(e, "layer launch");
   b->layers_done += 1;
@@ -235,10 +237,10 @@ int mps_apply_layers(mps_batch* b, int32_t count, const double* theta, const dou
   hipError_t e;
   if (b->precision == MPS_PREC_FP64)
     e = launch_layers<double>((double*)b->state, b->n_sites, b->chi, S, b->layers_done, count,
-                              b->batch, theta, phi, trunc_err, b->status, stream);
+                              b->batch, theta, phi, trunc_err, b->status, b->n_layers, stream);
   else
     e = launch_layers<float>((float*)b->state, b->n_sites, b->chi, S, b->layers_done, count,
-                             b->batch, theta, phi, trunc_err, b->status, stream);
+                             b->batch, theta, phi, trunc_err, b->status, b->n_layers, stream);
   if (e != hipSuccess) return check_hip(e, "layer launch");
   b->layers_done += count;
   return ok();

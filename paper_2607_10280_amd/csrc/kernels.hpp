@@ -17,11 +17,11 @@ hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch
 template <typename T>
 hipError_t launch_layers(T* state, int n, int chi, int S, int layer, int count, int batch,
                          const double* theta, const double* phi, double* trunc_err, int* status,
-                         hipStream_t stream);
+                         int n_layers, hipStream_t stream);
 template <typename T>
 hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, int program,
                         const double* theta, const double* phi, const double* pixels,
-                        double* trunc_err, int* status, hipStream_t stream);
+                        double* trunc_err, int* status, int n_layers, hipStream_t stream);
 
 // Bonds and ladder layers that keep all their singular values: kExactMpo (default) applies such
 // a layer as one site-local contraction and splits other such bonds exactly; kExactQr splits
@@ -51,10 +51,17 @@ hipError_t launch_measure16(const void* state, void* env, const int* pairs, int 
 // workgroup per image and the per-bond matrices in an FP64 workspace of
 // wide_workspace_bytes(S) bytes per image (placed by the library after the environments).
 size_t wide_workspace_bytes(int S);
+// A wide-slot layer that keeps every singular value as the parity product operator (ws: the
+// batch's FP64 workspace, ws_stride complex128 elements per image); false when not applicable.
+template <typename T>
+bool launch_mpo_wide(T* state, double* ws, size_t ws_stride, int n, int chi, int S, int layer,
+                     int batch, int program, const double* theta, const double* phi,
+                     const double* pixels, double* trunc_err, int* status, int n_layers,
+                     hipStream_t stream, hipError_t& err);
 template <typename T>
 hipError_t launch_layer_wide(T* state, double* ws, int n, int chi, int S, int layer, int batch,
                              int program, const double* theta, const double* phi,
-                             const double* pixels, double* trunc_err, int* status,
+                             const double* pixels, double* trunc_err, int* status, int n_layers,
                              hipStream_t stream);
 template <typename T>
 hipError_t launch_measure_wide(const T* state, T* env, double* ws, const int* pairs, int m, int n,

@@ -847,6 +847,14 @@ __host__ __device__ inline bool layer_keeps_all(int n, int chi, int layer) {
   return true;
 }
 
+// True when the layer after `layer` truncates (within the batch's n_layers).  The last exact
+// layer before it then takes the QR sweep rather than the parity-operator contraction: the
+// truncating layer's Jacobi SVDs converge in fewer sweeps from the canonical gauge the QR sweep
+// leaves (measured: 7x7, L = 4, chi = 8, and the chi = 64 sweep cell at L = 7).
+__host__ __device__ inline bool next_truncates(int n, int chi, int layer, int n_layers) {
+  return layer + 1 < n_layers && !layer_keeps_all(n, chi, layer + 1);
+}
+
 // A ladder layer without truncation (layer_keeps_all): one left-to-right sweep.  Site 0 takes
 // its gate in FP64, then for each bond k the gated neighbour U_{k+1} A[k+1] (the gate commutes
 // with the CNOTs on the bonds to its left) is contracted with the centre into
@@ -1036,16 +1044,28 @@ __device__ __forceinline__ MpoBufs<T> mpo_bufs(LayerShared<S, T>& sh) {
   return MpoBufs<T>{{sh.mat, sh.mat + S * 2 * S}, {sh.uq, sh.ta}, sh.tb};
 }
 
-template <int S, typename T, typename Before, typename After>
+// Stage: how the old site tensor reaches tb (SitePrefetch: registers, loaded ahead; for slots
+// wider than 16, WideStage: a direct copy).  GLOBAL_BUFS: the carries and tb live in global
+// memory (the wide slots' workspace), so steps are ordered with a full barrier, whose fence
+// makes the lanes' global stores visible, instead of an LDS-only wait.
+template <int S, typename T, typename Before, typename After, typename Stage = SitePrefetch<S, T>,
+          bool GLOBAL_BUFS = false>
 __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, After dnew,
                          const MpoPlan& plan, const double* theta, const double* phi,
-                         SitePrefetch<S, T>& pf, int part, int gmode = kGateRyRz,
+                         Stage& pf, int part, int gmode = kGateRyRz,
                          const double* pix = nullptr, bool brick = false, int extra_lo = 0,
                          int extra_hi = -1) {
   constexpr size_t SLOT = (size_t)2 * S * S * 2;
   constexpr int CS = 2 * S;  // row stride of the left carry (columns <= 2 S)
   constexpr int SP = LayerShared<S, T>::SP;
   const int tid = threadIdx.x, kl = plan.kl, kr = plan.kr;
+  auto step_sync = [] {
+    if constexpr (GLOBAL_BUFS) {
+      __syncthreads();
+    } else {
+      lds_sync();
+    }
+  };
   const bool meet = kl + 1 == kr;
   if (part == 1 && meet) return false;
   const bool do_left = part != 1, do_right = part != 0 || meet;
@@ -1079,14 +1099,14 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
   bool bad = false;
   // Sites are loaded two steps ahead (pf: the next step's site, pf2: the one after), and the next
   // site's gate is computed while this step runs: each step is short next to a load's latency.
-  SitePrefetch<S, T> pf2;
+  Stage pf2 = pf;
   pf.load(st + (size_t)site_at(0) * SLOT, dold(site_at(0) - 1), dold(site_at(0)));
   if (total > 1) pf2.load(st + (size_t)site_at(1) * SLOT, dold(site_at(1) - 1), dold(site_at(1)));
   Gate2 gnext = site_gate(gmode, site_at(0), theta, phi, pix);
   for (int t = 0; t < total; ++t) {
     const int k = site_at(t);
     pf.commit(tb);
-    lds_sync();
+    step_sync();
     const Gate2 g = gnext;
     pf = pf2;
     if (t + 2 < total) {
@@ -1160,7 +1180,7 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
           for (int i = 0; i < L; ++i) cfma(acc, C[an * CS + i], gated_at(at, g, fdp.r(i), y ^ fdp.q(i), bp));
           V[idx] = acc;
         }
-        lds_sync();
+        step_sync();
         for (int idx = tid; idx < rows * 2 * cols; idx += kLayerThreads) {
           const int row = fc.q(idx), j = fc.r(idx), r = row >> 1, y = row & 1;
           cd acc{0.0, 0.0};
@@ -1198,7 +1218,7 @@ __device__ bool mpo_ends(const MpoBufs<T>& bufs, T* st, int n, Before dold, Afte
         }
       }
     }
-    lds_sync();
+    step_sync();
   }
   // identity tensors of the reduced sites
   for (int k = 0; k < nl; ++k) {
@@ -1261,7 +1281,7 @@ template <int S, typename T, bool WITH_MPO>
 __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n, int chi, int layer,
                                             int program, const double* theta, const double* phi,
                                             const double* pix, double* trunc_err, int* status,
-                                            int exact_qr) {
+                                            int exact_qr, int n_layers) {
   auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
   auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
   SitePrefetch<S, T> pf;
@@ -1274,7 +1294,8 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
     flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf, exact_qr);
   } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
     MpoPlan plan;
-    if (WITH_MPO && exact_qr == kExactMpo && mpo_plan(n, dold, dnew, plan))
+    if (WITH_MPO && exact_qr == kExactMpo && !next_truncates(n, chi, layer, n_layers) &&
+        mpo_plan(n, dold, dnew, plan))
       flags |= mpo_layer<S, T>(sh, st, n, dold, dnew, plan, theta, phi, trunc_err, pf);
     else
       flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
@@ -1296,7 +1317,8 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer(T* state, int n, int ch
   T* st = state + (size_t)b * n * ((size_t)2 * S * S * 2);
   layer_chain<S, T, false>(sh, st, n, chi, layer, PROG, theta, phi,
                     pixels ? pixels + (size_t)b * n : nullptr,
-                    trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b, exact_qr);
+                    trunc_err ? trunc_err + (size_t)b * (n - 1) : nullptr, status + b, exact_qr,
+                    0);
 }
 
 // A layer that keeps every singular value, batched: the ends (two workgroups per image, the
@@ -1415,7 +1437,8 @@ __global__ __launch_bounds__(kLayerThreads) void k_layer_mixed(const mps_request
     const double* phi = uniform_ptr(r->phi) + (size_t)layer * n;
     double* te = uniform_ptr(r->trunc_err);
     layer_chain<S, T, true>(sh, uniform_ptr((T*)r->state), n, chi, layer, kLayerRyRzLadder, theta, phi,
-                      nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1, exact_qr);
+                      nullptr, te ? te + (size_t)layer * (n - 1) : nullptr, ctrl + 1, exact_qr,
+                      n_layers);
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = layer + 1;
   }
@@ -1501,12 +1524,13 @@ hipError_t launch_encode(T* state, const double* pixels, int n, int S, int batch
 template <typename T>
 hipError_t launch_layer(T* state, int n, int chi, int S, int layer, int batch, int program,
                         const double* theta, const double* phi, const double* pixels,
-                        double* trunc_err, int* status, hipStream_t stream) {
+                        double* trunc_err, int* status, int n_layers, hipStream_t stream) {
   const dim3 grid(batch), block(kLayerThreads);
   MpoPlan plan;
   // the brickwork program takes the site-local form when its two end carries land on two
   // different sites (its even-site bit rule is not in the meeting-carries step)
   if (g_exact_qr == kExactMpo && layer_keeps_all(n, chi, layer) &&
+      !next_truncates(n, chi, layer, n_layers) &&
       mpo_plan(n, [&](int k) { return bond_dim(n, chi, layer, k); },
                [&](int k) { return bond_dim(n, chi, layer + 1, k); }, plan) &&
       (program == kLayerRyRzLadder || (program == kLayerHRyBrickwork && plan.kl + 1 < plan.kr))) {
@@ -1666,7 +1690,7 @@ __global__ __launch_bounds__(kLayerThreads) void k_mpo_run_core(T* state, int n,
 // Length of the run of layers from `layer` (at most max_count) that can go through the two run
 // kernels: every layer keeps all its singular values, and some sites lie between the reduced
 // ends in all of them.  Fills `run`.  0 when the layer at `layer` cannot start such a run.
-int mpo_run(int n, int chi, int S, int layer, int max_count, MpoRun& run) {
+int mpo_run(int n, int chi, int S, int layer, int max_count, int n_layers, MpoRun& run) {
   if (g_exact_qr != kExactMpo || S > kMaxBond) return 0;
   run.layer0 = layer;
   run.core_lo = 0;
@@ -1675,7 +1699,7 @@ int mpo_run(int n, int chi, int S, int layer, int max_count, MpoRun& run) {
   while (count < max_count && count < kMaxRun) {
     const int l = layer + count;
     MpoPlan p;
-    if (!layer_keeps_all(n, chi, l) ||
+    if (!layer_keeps_all(n, chi, l) || next_truncates(n, chi, l, n_layers) ||
         !mpo_plan(n, [&](int k) { return bond_dim(n, chi, l, k); },
                   [&](int k) { return bond_dim(n, chi, l + 1, k); }, p))
       break;
@@ -1768,20 +1792,20 @@ hipError_t launch_mpo_run(T* state, int n, int chi, int S, const MpoRun& run, in
 template <typename T>
 hipError_t launch_layers(T* state, int n, int chi, int S, int layer, int count, int batch,
                          const double* theta, const double* phi, double* trunc_err, int* status,
-                         hipStream_t stream) {
+                         int n_layers, hipStream_t stream) {
   int r = 0;
   while (r < count) {
     const double* th = theta + (size_t)r * n;
     const double* ph = phi + (size_t)r * n;
     double* te = trunc_err ? trunc_err + (size_t)r * batch * (n - 1) : nullptr;
     MpoRun run;
-    const int len = mpo_run(n, chi, S, layer + r, count - r, run);
+    const int len = mpo_run(n, chi, S, layer + r, count - r, n_layers, run);
     hipError_t e;
     if (len >= 2) {
       e = launch_mpo_run<T>(state, n, chi, S, run, batch, th, ph, te, status, stream);
     } else {
       e = launch_layer<T>(state, n, chi, S, layer + r, batch, kLayerRyRzLadder, th, ph, nullptr,
-                          te, status, stream);
+                          te, status, n_layers, stream);
     }
     if (e != hipSuccess) return e;
     r += len >= 2 ? len : 1;
@@ -1789,16 +1813,138 @@ hipError_t launch_layers(T* state, int n, int chi, int S, int layer, int count, 
   return hipSuccess;
 }
 
+// ----------------------------------------------------------------- exact layers, slots above 16
+// The same contraction for slots of 32..128.  A site tensor of up to 128 x 2 x 128 cannot be
+// prefetched into registers, so the ends copy each old tensor into a buffer (WideStage) and keep
+// their carries in the image's FP64 workspace (the wide kernels' HBM/L2 workspace); the sites
+// between stage their old tensor in dynamic LDS with 256 lanes each.
+template <int S, typename T>
+struct WideStage {
+  static constexpr int SP = S + 1;
+  const T* src = nullptr;
+  int Dl = 0, Dr = 0;
+  __device__ void load(const T* slot, int dl, int dr) {
+    src = slot;
+    Dl = dl;
+    Dr = dr;
+  }
+  __device__ void commit(cx<T>* dst) const {
+    for (int idx = threadIdx.x; idx < Dl * 2 * Dr; idx += kLayerThreads) {
+      const int row = idx / Dr, b = idx - row * Dr;
+      dst[row * SP + b] = cx<T>{src[2 * ((size_t)row * S + b)], src[2 * ((size_t)row * S + b) + 1]};
+    }
+  }
+};
+
+// Two workgroups per image (left end, right end; one when the carries meet), one wavefront
+// each.  Workspace of an image: left carries, right carries (2 S^2 complex128 each, two of
+// each), then the two parts' staged tensors.
+template <int S, typename T>
+__global__ __launch_bounds__(kLayerThreads) void k_mpo_ends_wide(
+    T* state, cd* ws, size_t ws_stride, int n, int chi, int layer, MpoPlan plan,
+    const double* theta, const double* phi, const double* pixels, int brick, double* trunc_err,
+    int* status, int batch) {
+  const int b = blockIdx.x >> 1, part = blockIdx.x & 1;
+  if (b >= batch) return;
+  cd* wsb = ws + (size_t)b * ws_stride;
+  cd* c0 = wsb;
+  cd* r0 = wsb + 4 * S * S;
+  cx<T>* tb = reinterpret_cast<cx<T>*>(wsb + 8 * S * S) + (size_t)part * 2 * S * (S + 1);
+  const MpoBufs<T> bufs{{c0, c0 + 2 * S * S}, {r0, r0 + 2 * S * S}, tb};
+  auto dold = [&](int k) { return bond_dim(n, chi, layer, k); };
+  auto dnew = [&](int k) { return bond_dim(n, chi, layer + 1, k); };
+  if (part == 0 && trunc_err)
+    for (int k = threadIdx.x; k < n - 1; k += kLayerThreads) trunc_err[(size_t)b * (n - 1) + k] = 0.0;
+  WideStage<S, T> pf;
+  const bool bad = mpo_ends<S, T, decltype(dold), decltype(dnew), WideStage<S, T>, true>(
+      bufs, state + (size_t)b * n * ((size_t)2 * S * S * 2), n, dold, dnew, plan, theta, phi, pf,
+      part, brick ? kGateHRy : kGateRyRz, pixels ? pixels + (size_t)b * n : nullptr, brick != 0);
+  if (__any(bad) && threadIdx.x == 0) atomicOr(status + b, kImgNonfinite);
+}
+
+constexpr int kWideSiteThreads = 256;
+
+template <int S, typename T>
+__global__ __launch_bounds__(kWideSiteThreads) void k_mpo_sites_wide(
+    T* state, int n, int chi, int layer, MpoPlan plan, const double* theta, const double* phi,
+    const double* pixels, int brick, int* status, int batch) {
+  constexpr size_t SLOT = (size_t)2 * S * S * 2;
+  extern __shared__ unsigned char wide_lds[];
+  cx<T>* old = reinterpret_cast<cx<T>*>(wide_lds);
+  const int nmid = plan.kr - plan.kl - 2;
+  const int b = blockIdx.x / nmid, k = plan.kl + 2 + blockIdx.x % nmid;
+  if (b >= batch) return;
+  const int tid = threadIdx.x;
+  const int Dp = bond_dim(n, chi, layer, k - 1), Do = bond_dim(n, chi, layer, k);
+  T* slot = state + ((size_t)b * n + k) * SLOT;
+  for (int idx = tid; idx < Dp * 2 * Do; idx += kWideSiteThreads) {
+    const int row = idx / Do, c = idx - row * Do;
+    old[idx] = cx<T>{slot[2 * ((size_t)row * S + c)], slot[2 * ((size_t)row * S + c) + 1]};
+  }
+  __syncthreads();
+  auto at = [&](int a, int s_, int c) { return to_cd(old[(a * 2 + s_) * Do + c]); };
+  const Gate2 g = site_gate(brick ? kGateHRy : kGateRyRz, k, theta, phi,
+                            pixels ? pixels + (size_t)b * n : nullptr);
+  const bool bad = mpo_plain_site<S, T>(at, g, Dp, Do, slot, tid, kWideSiteThreads, k, brick != 0);
+  if (__any(bad) && (tid & 63) == 0) atomicOr(status + b, kImgNonfinite);
+}
+
+// Launches the contraction for a wide-slot layer that keeps every singular value; false (and
+// nothing launched) when the layer takes the canonical sweep path instead.
+template <typename T>
+bool launch_mpo_wide(T* state, double* ws, size_t ws_stride, int n, int chi, int S, int layer,
+                     int batch, int program, const double* theta, const double* phi,
+                     const double* pixels, double* trunc_err, int* status, int n_layers,
+                     hipStream_t stream, hipError_t& err) {
+  MpoPlan plan;
+  if (g_exact_qr != kExactMpo || !layer_keeps_all(n, chi, layer) ||
+      next_truncates(n, chi, layer, n_layers) ||
+      !mpo_plan(n, [&](int k) { return bond_dim(n, chi, layer, k); },
+                [&](int k) { return bond_dim(n, chi, layer + 1, k); }, plan))
+    return false;
+  if (program != kLayerRyRzLadder && !(program == kLayerHRyBrickwork && plan.kl + 1 < plan.kr))
+    return false;
+  const int brick = program == kLayerHRyBrickwork;
+  const int nmid = plan.kr - plan.kl - 2;
+  const size_t lds = (size_t)(S / 2) * 2 * (S / 2) * sizeof(cx<T>);
+  switch (S) {
+#define ANOMPS_KW(SV)                                                                              \
+  case SV:                                                                                         \
+    hipLaunchKernelGGL((k_mpo_ends_wide<SV, T>), dim3(2 * batch), dim3(kLayerThreads), 0, stream,  \
+                       state, (cd*)ws, ws_stride, n, chi, layer, plan, theta, phi, pixels, brick,  \
+                       trunc_err, status, batch);                                                  \
+    if (nmid > 0)                                                                                  \
+      hipLaunchKernelGGL((k_mpo_sites_wide<SV, T>), dim3((unsigned)(batch * nmid)),               \
+                         dim3(kWideSiteThreads), lds, stream, state, n, chi, layer, plan, theta,   \
+                         phi, pixels, brick, status, batch);                                       \
+    break;
+    ANOMPS_KW(32) ANOMPS_KW(64) ANOMPS_KW(128)
+#undef ANOMPS_KW
+    default: return false;
+  }
+  err = hipGetLastError();
+  return true;
+}
+
+template bool launch_mpo_wide<double>(double*, double*, size_t, int, int, int, int, int, int,
+                                      const double*, const double*, const double*, double*, int*,
+                                      int, hipStream_t, hipError_t&);
+template bool launch_mpo_wide<float>(float*, double*, size_t, int, int, int, int, int, int,
+                                     const double*, const double*, const double*, double*, int*,
+                                     int, hipStream_t, hipError_t&);
+
 template hipError_t launch_encode<double>(double*, const double*, int, int, int, int*, hipStream_t);
 template hipError_t launch_encode<float>(float*, const double*, int, int, int, int*, hipStream_t);
 template hipError_t launch_layer<double>(double*, int, int, int, int, int, int, const double*,
-                                         const double*, const double*, double*, int*, hipStream_t);
+                                         const double*, const double*, double*, int*, int,
+                                         hipStream_t);
 template hipError_t launch_layer<float>(float*, int, int, int, int, int, int, const double*,
-                                        const double*, const double*, double*, int*, hipStream_t);
+                                        const double*, const double*, double*, int*, int,
+                                        hipStream_t);
 template hipError_t launch_layers<double>(double*, int, int, int, int, int, int, const double*,
-                                          const double*, double*, int*, hipStream_t);
+                                          const double*, double*, int*, int, hipStream_t);
 template hipError_t launch_layers<float>(float*, int, int, int, int, int, int, const double*,
-                                         const double*, double*, int*, hipStream_t);
+                                         const double*, double*, int*, int, hipStream_t);
 template hipError_t launch_encode_mixed<double>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_encode_mixed<float>(const mps_request*, int, int, int, hipStream_t);
 template hipError_t launch_layer_mixed<double>(const mps_request*, int, int, int, int*, int, hipStream_t);

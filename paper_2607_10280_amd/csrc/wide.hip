@@ -827,9 +827,13 @@ size_t wide_workspace_bytes(int S) { return ws_elems(S) * sizeof(cd); }
 template <typename T>
 hipError_t launch_layer_wide(T* state, double* ws, int n, int chi, int S, int layer, int batch,
                              int program, const double* theta, const double* phi,
-                             const double* pixels, double* trunc_err, int* status,
+                             const double* pixels, double* trunc_err, int* status, int n_layers,
                              hipStream_t stream) {
   if (S <= kMaxBond || S > 128) return hipErrorInvalidValue;
+  hipError_t err = hipSuccess;
+  if (launch_mpo_wide<T>(state, ws, ws_elems(S), n, chi, S, layer, batch, program, theta, phi,
+                         pixels, trunc_err, status, n_layers, stream, err))
+    return err;
   if (program == 1)
     hipLaunchKernelGGL((k_layer_wide<T, 1>), dim3(batch), dim3(kWT), 0, stream, state, (cd*)ws, n,
                        chi, S, layer, theta, phi, pixels, trunc_err, status, exact_qr());
@@ -854,10 +858,10 @@ hipError_t launch_measure_wide(const T* state, T* env, double* ws, const int* pa
 
 template hipError_t launch_layer_wide<double>(double*, double*, int, int, int, int, int, int,
                                               const double*, const double*, const double*, double*,
-                                              int*, hipStream_t);
+                                              int*, int, hipStream_t);
 template hipError_t launch_layer_wide<float>(float*, double*, int, int, int, int, int, int,
                                              const double*, const double*, const double*, double*,
-                                             int*, hipStream_t);
+                                             int*, int, hipStream_t);
 template hipError_t launch_measure_wide<double>(const double*, double*, double*, const int*, int,
                                                 int, int, int, int, int, double*, hipStream_t);
 template hipError_t launch_measure_wide<float>(const float*, float*, double*, const int*, int, int,

@@ -51,6 +51,13 @@ def mpo_plan(n: int, chi: int, layer: int):
     return kl, kr
 
 
+def next_truncates(n: int, chi: int, layer: int, n_layers: int) -> bool:
+    """True when layer `layer` + 1 exists and truncates.  The library then applies layer
+    `layer` by the QR sweep even in mode "mpo" (the canonical gauge it leaves lets the
+    truncating layer's Jacobi SVDs converge in fewer sweeps)."""
+    return layer + 1 < n_layers and not layer_keeps_all(n, chi, layer + 1)
+
+
 def householder_qr_flops(m: int, n: int) -> float:
     """Complex Householder QR of an m x n matrix (m >= n) with Q formed explicitly: each
     reflector costs a dot product and an update over the remaining columns and rows, once to
@@ -58,7 +65,7 @@ def householder_qr_flops(m: int, n: int) -> float:
     return CMAC * 4.0 * sum((n - j) * (m - j) for j in range(n))
 
 
-def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo") -> dict:
+def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo", n_layers: int | None = None) -> dict:
     """Work of applying layer `layer` (0-based) to one image.  mode "mpo" (a layer that keeps
     every singular value, applied as the parity product operator): the gate on every old
     tensor, the left and right carries over the reduced chain ends and their product into the
@@ -67,7 +74,10 @@ def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo") -> dict:
     two-site matrix), else contract Theta' and split it by Householder QR (or not at all when D
     equals its row count).  Otherwise, and for mode "svd": canonical sweep (gate + SVD of each
     site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left neighbour), then the ladder
-    (two-site contraction, SVD, U^H Theta' for the new centre)."""
+    (two-site contraction, SVD, U^H Theta' for the new centre).  With n_layers given, mode
+    "mpo" counts a layer followed by a truncating one as mode "qr", as the library runs it."""
+    if mode == "mpo" and n_layers is not None and next_truncates(n, chi, layer, n_layers):
+        mode = "qr"
     d_old = lambda k: bond(n, chi, layer, k)
     d_new = lambda k: bond(n, chi, layer + 1, k)
     plan = mpo_plan(n, chi, layer) if mode == "mpo" else None
