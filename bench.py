@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # one mps_apply_layers call (all four layers): k_mpo_run_core + k_mpo_run_ends
     "layers": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-               "sha1": "28194a05ecea28bdecd15c0f2f0392dc7972ce8a",
-               "bytes": ((2 * 5319.4 + 167936.0) + (2 * 5053.2 + 6118.7)) * 1024},
+               "sha1": "0907698710102818f3f2e5ee101d2b7c003502cf",
+               "bytes": ((2 * 5316.0 + 167936.0) + (2 * 4975.3 + 6277.2)) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "ea0c34a60e032bda24de21e4cd0d4a1dbacc1bde",
-                "bytes": (2 * (194891.9 + 236586.9) + (204801.2 + 5904.2)) * 1024},
+                "sha1": "51f4562a590a9821032233df6fdf399ab33755c1",
+                "bytes": (2 * (194788.5 + 232401.3) + (204801.1 + 6013.6)) * 1024},
 }
 
 
@@ -73,11 +73,13 @@ def parse():
     ap.add_argument("--no-svd-compare", action="store_true",
                     help="skip the extra timing with every layer through the SVD ladder")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "mixed", "serve", "grid", "paper", "chisweep"],
+                    choices=["headline", "mixed", "serve", "grid", "paper", "chisweep",
+                             "precision"],
                     help="headline: the 7x7 L=4 chi=16 batch; mixed: 4096 requests of mixed size "
                          "and depth through the persistent mixed-table launches; serve: Poisson "
                          "arrivals through the continuous-batching loop; chisweep: feature error "
-                         "and cost against chi at 7x7, L=7 (chi=128 is exact)")
+                         "and cost against chi at 7x7, L=7 (chi=128 is exact); precision: FP32 "
+                         "against split-BF16 errors per (L, chi) at 16x16")
     ap.add_argument("--requests", type=int, default=0, help="mixed/serve: number of requests")
     ap.add_argument("--tune-cache", default="", help="mixed/serve: autotuner JSON cache path")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -465,6 +467,76 @@ def run_chisweep(args):
         "cells": cells}))
 
 
+def run_precision(args):
+    """FP32 against split-BF16 contractions on 16x16 images (256 qubits), batch 256: for
+    L in {1, 2} x chi in {16, 32, 64} the max abs error of sampled images against the FP64
+    untruncated MPS oracle, with the batch time of each precision.  At these depths every bond
+    is at most 2^L = 4 wide (the bond rule), so these cells run the vector contractions of
+    slot 2 and 4, where the split-BF16 variant does not apply and both precisions give the same
+    numbers; one more cell, L = 4 and chi = 16 (slot 16, every bond up to 16 wide), runs the
+    matrix-core contractions where the two precisions differ."""
+    import torch
+    from paper_2607_10280_amd import anomps, inputs
+    from oracle import features as ofeat
+    p = 16
+    B = args.batch if args.batch != 1024 else 256
+    n = p * p
+    x = inputs.blob_images(B, p, 21)
+    pairs = inputs.neighbour_pairs(p)
+    pd = torch.as_tensor(pairs, device="cuda")
+    pix = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    sample = [0, B // 3, (2 * B) // 3, B - 1]
+    grid = [(L, chi) for L in (1, 2) for chi in (16, 32, 64)] + [(4, 16)]
+    refs, angles = {}, {}
+    for L in sorted({L for L, _ in grid}):
+        th, ph = inputs.layer_angles(L, n, 22 + L)
+        angles[L] = (torch.as_tensor(th, device="cuda").contiguous(),
+                     torch.as_tensor(ph, device="cuda").contiguous())
+        refs[L] = ofeat.exact_features(x[sample], th, ph, pairs)
+    cells = []
+    for L, chi in grid:
+        thd, phd = angles[L]
+        cell = {"L": L, "chi": chi, "slot": anomps.slot_dim(n, chi, L),
+                "in_configured_grid": L <= 2}
+        for name in ("fp32", "split_bf16"):
+            prec = anomps.PRECISIONS[name]
+            b = anomps.new_batch(n, chi, L, B, prec)
+            out = torch.empty((B, len(pairs), 15), dtype=torch.float32, device="cuda")
+
+            def step():
+                anomps.init_batch(b, pix)
+                anomps.apply_layers(b, thd, phd)
+                anomps.pauli_pair_expect(b, pd, out)
+            step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            o = out.double().cpu().numpy()[sample]
+            cell[name] = {"ms": round(ms, 3), "images_per_s": round(B / (ms * 1e-3), 1),
+                          "max_abs_err": float(np.abs(o - refs[L]).max()),
+                          "status_nonzero": int(np.count_nonzero(b.status.cpu()))}
+            del b, out
+        cells.append(cell)
+        print(f"[precision] L={L} chi={chi} fp32 {cell['fp32']['max_abs_err']:.2e} "
+              f"split {cell['split_bf16']['max_abs_err']:.2e}", file=sys.stderr, flush=True)
+    worst = max(c["split_bf16"]["max_abs_err"] for c in cells)
+    print(json.dumps({
+        "metric": "max abs Pauli-expectation error vs the FP64 MPS oracle per (L, chi), FP32 and "
+                  "split-BF16 contractions, 16x16",
+        "value": worst, "unit": "abs error (split-BF16, worst cell)", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": False, "data": "synthetic",
+        "dtype": "c64+f64svd / split_bf16",
+        "config": {"workload": f"{p}x{p} Gaussian blobs, L in {{1,2}} x chi in {{16,32,64}} "
+                               f"(+ L=4, chi=16), {len(pairs)} H+V pairs", "global_batch": B,
+                   "sampled_images": len(sample)},
+        "cells": cells}))
+
+
 # ----------------------------------------------------------------------------- main
 def main():
     args = parse()
@@ -481,6 +553,8 @@ def main():
         return run_paper(args)
     if args.workload == "chisweep":
         return run_chisweep(args)
+    if args.workload == "precision":
+        return run_precision(args)
     import torch
     from paper_2607_10280_amd import anomps, inputs, workload
 

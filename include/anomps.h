@@ -181,16 +181,19 @@ int mps_apply_layers(mps_batch* b, int32_t count, const double* theta, const dou
  *    layer being unitary); the measurement contracts both environments and needs no gauge.
  *    The brickwork program of mps_apply_layer_program takes the same form (one bit per bond:
  *    an even site passes its input bit, an odd site its output bit) unless its two end carries
- *    land on one site.  Slots wider than 16 take these layers like the truncating ones (next
- *    paragraph).
+ *    land on one site.  Slots wider than 16 take the same contraction (the carries in the
+ *    batch's FP64 workspace).  A layer that keeps every singular value but is followed, in the
+ *    batch's n_layers, by a truncating layer takes the MPS_EXACT_QR path instead: the
+ *    truncating layer's SVDs converge faster from the canonical gauge that path leaves.
  *  MPS_EXACT_QR: one left-to-right sweep; each two-site matrix Theta' is split exactly, by
  *    Householder QR in FP64 (A[k] <- Q, centre <- R) or, when D_k equals its row count, as
  *    A[k] <- identity, centre <- Theta'; the one-qubit gates are applied as each site is
  *    reached and the last centre is scaled to unit norm.
  *  MPS_EXACT_SVD: the canonical sweep + Jacobi SVD ladder, as for every other layer.
- * Layers with any truncating bond and slots wider than 16 keep the canonical sweep; under MPS_EXACT_MPO and MPS_EXACT_QR their ladder still splits each bond
- * that keeps all min(rows, cols) singular values exactly (identity or QR, centre renormalised
- * by |Theta'|) and runs the Jacobi SVD only where weight can be discarded.  Process-wide
+ * Layers with any truncating bond keep the canonical sweep (so do slots wider than 16 under
+ * MPS_EXACT_QR); under MPS_EXACT_MPO and MPS_EXACT_QR their ladder still splits each bond that
+ * keeps all min(rows, cols) singular values exactly (identity or QR, centre renormalised by
+ * |Theta'|) and runs the Jacobi SVD only where weight can be discarded.  Process-wide
  * setting, read at each launch.  Returns MPS_ERR_INVALID_ARG for another mode.
  */
 enum { MPS_EXACT_QR = 0, MPS_EXACT_SVD = 1, MPS_EXACT_MPO = 2 };

@@ -26,7 +26,8 @@ constexpr size_t kSlotAlign = 64;        // complex128 elements (1 KiB)
 
 // Workspace per image in complex128 elements: the larger of the layer's (ta, tb [2S^2] each,
 // mat [4S^2], uq [2S^2], xb [2S^2]), the environments' (E [S^2] + Tm [2S^2] per side) and the
-// pairs' (kWideGroups workgroups of F [3S^2] + Tm [6S^2] + G [3S^2]).
+// pairs' (kWideGroups workgroups of F [3S^2] + Tm [6S^2] + G [3S^2]; F^{00}, F^{01} and four
+// Tm blocks in use).
 __host__ __device__ size_t ws_elems(int S) {
   const size_t s2 = (size_t)S * S;
   size_t e = 12 * s2;
@@ -663,9 +664,11 @@ __device__ __forceinline__ cd pauli_w(int a, int r, int c) {
 }
 
 // Pair expectations: workgroup (image, g) takes the start sites i = g, g + G, ...; for each it
-// opens the three independent blocks F^{00}, F^{01}, F^{11} (F^{10} = F^{01 H}) from L_i and
-// A[i], carries them through the transfer maps of the sites up to each listed partner j, closes
-// with A[j] and R_{j+1} into rho_ij and writes Re Tr(rho_ij P_a (x) P_c).
+// opens the blocks F^{00} and F^{01} (F^{10} = F^{01 H}) from L_i and A[i], carries them through
+// the transfer maps of the sites up to each listed partner j, closes with A[j] and R_{j+1} into
+// rho_ij and writes Re Tr(rho_ij P_a (x) P_c).  F^{11} is not carried: the two diagonal blocks
+// sum to the left environment at every step (the open and the transfer maps are linear and
+// take L_i to L_{i+1}, L_{i+2}, ...), so at the close F^{11} = L_j - F^{00}.
 template <typename T>
 __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env, cd* ws,
                                                     const int* pairs, int m, int n, int chi, int S,
@@ -728,8 +731,8 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
                    [&](int ap, int cp) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + sp) * S + cp)); },
                    [&](int a, int cp, cd v) { Tm[(size_t)(sp * S + a) * S + cp] = v; });
       __syncthreads();
-      for (int blk = 0; blk < 3; ++blk) {
-        const int s = blk == 2 ? 1 : 0, sp = blk == 0 ? 0 : 1;
+      for (int blk = 0; blk < 2; ++blk) {
+        const int s = 0, sp = blk;
         tile_cgemm(Dc, Dc, Dl, [&](int c, int a) { return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
                    [&](int a, int cp) { return Tm[(size_t)(sp * S + a) * S + cp]; },
                    [&](int c, int cp, cd v) { F[(size_t)(blk * S + c) * S + cp] = v; });
@@ -742,14 +745,14 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       for (; cur < j; ++cur) {
         const int Dc = dim(cur - 1), Dn = dim(cur);
         const T* A = st + (size_t)cur * SLOT;
-        for (int bu = 0; bu < 6; ++bu) {
+        for (int bu = 0; bu < 4; ++bu) {
           const int blk = bu >> 1, u = bu & 1;
           tile_cgemm(Dc, Dn, Dc, [&](int c, int cp) { return F[(size_t)(blk * S + c) * S + cp]; },
                      [&](int cp, int ep) { return cconj(load_c<T, double>(A, (size_t)(cp * 2 + u) * S + ep)); },
                      [&](int c, int ep, cd v) { Tm[(size_t)(bu * S + c) * S + ep] = v; });
         }
         __syncthreads();
-        for (int blk = 0; blk < 3; ++blk)  // k runs over (u, c)
+        for (int blk = 0; blk < 2; ++blk)  // k runs over (u, c)
           tile_cgemm(Dn, Dn, 2 * Dc,
                      [&](int e, int k) { const int u = k >= Dc, c = k - (u ? Dc : 0);
                                          return load_c<T, double>(A, (size_t)(c * 2 + u) * S + e); },
@@ -778,13 +781,18 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       double part[32];
 #pragma unroll
       for (int e = 0; e < 32; ++e) part[e] = 0.0;
+      const T* Lj = evl + (size_t)j * s2 * 2;
       for (int idx = tid; idx < Dd * Dd; idx += kWT) {
         const int d = idx / Dd, dp = idx % Dd;
+        const cd f00 = F[(size_t)d * S + dp], lj = load_c<T, double>(Lj, (size_t)d * S + dp);
+        const cd f11{lj.re - f00.re, lj.im - f00.im};
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
           const cd f = (s == 1 && sp == 0) ? cconj(F[(size_t)(1 * S + dp) * S + d])
-                                           : F[(size_t)((s + sp) * S + d) * S + dp];
+                       : (s == 1)          ? f11
+                       : (sp == 1)         ? F[(size_t)(1 * S + d) * S + dp]
+                                           : f00;
           const cd gg = (t == 1 && tp == 0) ? cconj(G[(size_t)(1 * S + dp) * S + d])
                                             : G[(size_t)((t + tp) * S + d) * S + dp];
           const cd fg = cmul(f, gg);

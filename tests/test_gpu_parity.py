@@ -321,6 +321,24 @@ def test_split_bf16_contractions(A, p):
     assert err > 0  # the variant really runs (a bit-exact match would mean the FP32 path ran)
 
 
+@pytest.mark.parametrize("L,chi", [(1, 16), (2, 32), (2, 64)])
+def test_precision_grid_256_qubits(A, L, chi):
+    """16x16 images at shallow depth with a large bond limit: the bond rule caps every bond at
+    2^L, so FP32 and split-BF16 run the same vector contractions and both meet the FP32 bar."""
+    p = 16
+    n = p * p
+    x = inputs.blob_images(2, p, 180 + L)
+    th, ph = inputs.layer_angles(L, n, 181 + L)
+    pairs = inputs.neighbour_pairs(p)
+    ref = ofeat.exact_features(x, th, ph, pairs)
+    f32, st = run(A, x, th, ph, pairs, chi, A.PREC_FP32)
+    split, st2 = run(A, x, th, ph, pairs, chi, A.PREC_SPLIT_BF16)
+    assert A.slot_dim(n, chi, L) == 2 ** L
+    assert np.all(st == 0) and np.all(st2 == 0)
+    assert np.abs(f32 - ref).max() <= FP32_TOL
+    assert np.array_equal(split, f32)
+
+
 # ------------------------------------------------------------------ the paper's own circuit
 
 
