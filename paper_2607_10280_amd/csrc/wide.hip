@@ -579,11 +579,72 @@ __device__ __forceinline__ void tile_cgemm_t(int Mr, int Nc, int K, FA a, FB b, 
   }
 }
 
-// 4 x 4 tiles when there are enough of them for every lane, 2 x 2 otherwise.
+// LDS-staged form for outputs of 64 x 64 entries or more: the workgroup walks 64 x 64 output
+// blocks; per chunk of 16 k it stages the 64 x 16 slice of the left operand and the 16 x 64
+// slice of the right one in LDS (each operand entry read once per block instead of once per
+// lane tile), then each lane accumulates a 4 x 4 tile, rows tr + 16 ii and columns tc + 16 jj
+// (tr = lane / 16, tc = lane % 16), so that the 16 lanes of a row group read consecutive LDS
+// entries and store consecutive columns.  The k order of every sum is the plain 0..K-1, as in
+// tile_cgemm_t.  Every lane of the workgroup must call it (it holds barriers).
+constexpr int kGB = 64, kGK = 16, kGAS = kGB + 1;  // block, k chunk, padded row of the A slice
+struct GemmLds {
+  cd a[kGK * kGAS];  // a[kk][row], rows padded to 65 so that the staging stores miss no bank
+  cd b[kGK * kGB];   // b[kk][col]
+};
+
 template <typename FA, typename FB, typename FC>
-__device__ __forceinline__ void tile_cgemm(int Mr, int Nc, int K, FA a, FB b, FC out) {
-  if (Mr * Nc >= 16 * kWT)
-    tile_cgemm_t<4, 4>(Mr, Nc, K, a, b, out);
+__device__ void lds_cgemm(GemmLds& g, int Mr, int Nc, int K, FA a, FB b, FC out) {
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int bn = (Nc + kGB - 1) / kGB, nblk = ((Mr + kGB - 1) / kGB) * bn;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int i0 = (blk / bn) * kGB, j0 = (blk % bn) * kGB;
+    cd acc[4][4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = cd{0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += kGK) {
+#pragma unroll
+      for (int r = 0; r < kGB * kGK / kWT; ++r) {
+        const int idx = t + r * kWT;
+        const int ka = idx & (kGK - 1), row = idx >> 4;
+        g.a[ka * kGAS + row] =
+            (i0 + row < Mr && k0 + ka < K) ? a(i0 + row, k0 + ka) : cd{0.0, 0.0};
+        const int kb = idx >> 6, col = idx & (kGB - 1);
+        g.b[kb * kGB + col] =
+            (k0 + kb < K && j0 + col < Nc) ? b(k0 + kb, j0 + col) : cd{0.0, 0.0};
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < kGK; ++kk) {
+        cd av[4], bv[4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) av[ii] = g.a[kk * kGAS + tr + 16 * ii];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) bv[jj] = g.b[kk * kGB + tc + 16 * jj];
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) cfma(acc[ii][jj], av[ii], bv[jj]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + tr + 16 * ii, j = j0 + tc + 16 * jj;
+        if (i < Mr && j < Nc) out(i, j, acc[ii][jj]);
+      }
+  }
+}
+
+// LDS-staged blocks when the output has 64 x 64 entries or more, 2 x 2 lane tiles otherwise.
+// Called by every lane of the workgroup.
+template <typename FA, typename FB, typename FC>
+__device__ __forceinline__ void tile_cgemm(GemmLds& g, int Mr, int Nc, int K, FA a, FB b, FC out) {
+  if (Mr * Nc >= kGB * kGB)
+    lds_cgemm(g, Mr, Nc, K, a, b, out);
   else
     tile_cgemm_t<2, 2>(Mr, Nc, K, a, b, out);
 }
@@ -597,6 +658,7 @@ __global__ __launch_bounds__(kWT) void k_env_wide(const T* state, T* env, cd* ws
   const size_t SLOT = (size_t)2 * S * S * 2, s2 = (size_t)S * S;
   const T* st = state + (size_t)b * n * SLOT;
   T* ev = env + ((size_t)b * 2 + side) * (n + 1) * s2 * 2;
+  __shared__ GemmLds gl;
   cd* E = ws + (size_t)b * ws_elems(S) + (size_t)side * 3 * s2;
   cd* Tm = E + s2;
   const int tid = threadIdx.x;
@@ -616,12 +678,12 @@ __global__ __launch_bounds__(kWT) void k_env_wide(const T* state, T* env, cd* ws
       const T* A = st + (size_t)k * SLOT;
       // Tm[s][a][b'] = sum_a' E[a][a'] conj(A[a'][s][b'])
       for (int s = 0; s < 2; ++s)
-        tile_cgemm(Dl, Dr, Dl, [&](int a, int ap) { return E[(size_t)a * S + ap]; },
+        tile_cgemm(gl, Dl, Dr, Dl, [&](int a, int ap) { return E[(size_t)a * S + ap]; },
                    [&](int ap, int bp) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + bp)); },
                    [&](int a, int bp, cd v) { Tm[(size_t)(s * S + a) * S + bp] = v; });
       __syncthreads();
       // L_{k+1}[b][b'] = sum_s sum_a A[a][s][b] Tm[s][a][b']  (k runs over (s, a))
-      tile_cgemm(Dr, Dr, 2 * Dl,
+      tile_cgemm(gl, Dr, Dr, 2 * Dl,
                  [&](int bb, int k) { const int s = k >= Dl, a = k - (s ? Dl : 0);
                                       return load_c<T, double>(A, (size_t)(a * 2 + s) * S + bb); },
                  [&](int k, int bp) { const int s = k >= Dl, a = k - (s ? Dl : 0);
@@ -637,12 +699,12 @@ __global__ __launch_bounds__(kWT) void k_env_wide(const T* state, T* env, cd* ws
       const T* A = st + (size_t)k * SLOT;
       // Tm[s][c][a'] = sum_c' E[c][c'] conj(A[a'][s][c'])
       for (int s = 0; s < 2; ++s)
-        tile_cgemm(Dr, Dl, Dr, [&](int c, int cp) { return E[(size_t)c * S + cp]; },
+        tile_cgemm(gl, Dr, Dl, Dr, [&](int c, int cp) { return E[(size_t)c * S + cp]; },
                    [&](int cp, int ap) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + s) * S + cp)); },
                    [&](int c, int ap, cd v) { Tm[(size_t)(s * S + c) * S + ap] = v; });
       __syncthreads();
       // R_k[a][a'] = sum_s sum_c A[a][s][c] Tm[s][c][a']  (k runs over (s, c))
-      tile_cgemm(Dl, Dl, 2 * Dr,
+      tile_cgemm(gl, Dl, Dl, 2 * Dr,
                  [&](int a, int k) { const int s = k >= Dr, c = k - (s ? Dr : 0);
                                      return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
                  [&](int k, int ap) { const int s = k >= Dr, c = k - (s ? Dr : 0);
@@ -674,6 +736,7 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
                                                     const int* pairs, int m, int n, int chi, int S,
                                                     int layers, T* out) {
   __shared__ WideShared sh;
+  __shared__ GemmLds gl;
   const int b = blockIdx.x / kWideGroups, g = blockIdx.x % kWideGroups;
   const size_t SLOT = (size_t)2 * S * S * 2, s2 = (size_t)S * S;
   const T* st = state + (size_t)b * n * SLOT;
@@ -727,13 +790,13 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       const T* A = st + (size_t)i * SLOT;
       const T* Ev = evl + (size_t)i * s2 * 2;
       for (int sp = 0; sp < 2; ++sp)
-        tile_cgemm(Dl, Dc, Dl, [&](int a, int ap) { return load_c<T, double>(Ev, (size_t)a * S + ap); },
+        tile_cgemm(gl, Dl, Dc, Dl, [&](int a, int ap) { return load_c<T, double>(Ev, (size_t)a * S + ap); },
                    [&](int ap, int cp) { return cconj(load_c<T, double>(A, (size_t)(ap * 2 + sp) * S + cp)); },
                    [&](int a, int cp, cd v) { Tm[(size_t)(sp * S + a) * S + cp] = v; });
       __syncthreads();
       for (int blk = 0; blk < 2; ++blk) {
         const int s = 0, sp = blk;
-        tile_cgemm(Dc, Dc, Dl, [&](int c, int a) { return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
+        tile_cgemm(gl, Dc, Dc, Dl, [&](int c, int a) { return load_c<T, double>(A, (size_t)(a * 2 + s) * S + c); },
                    [&](int a, int cp) { return Tm[(size_t)(sp * S + a) * S + cp]; },
                    [&](int c, int cp, cd v) { F[(size_t)(blk * S + c) * S + cp] = v; });
       }
@@ -747,13 +810,13 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
         const T* A = st + (size_t)cur * SLOT;
         for (int bu = 0; bu < 4; ++bu) {
           const int blk = bu >> 1, u = bu & 1;
-          tile_cgemm(Dc, Dn, Dc, [&](int c, int cp) { return F[(size_t)(blk * S + c) * S + cp]; },
+          tile_cgemm(gl, Dc, Dn, Dc, [&](int c, int cp) { return F[(size_t)(blk * S + c) * S + cp]; },
                      [&](int cp, int ep) { return cconj(load_c<T, double>(A, (size_t)(cp * 2 + u) * S + ep)); },
                      [&](int c, int ep, cd v) { Tm[(size_t)(bu * S + c) * S + ep] = v; });
         }
         __syncthreads();
         for (int blk = 0; blk < 2; ++blk)  // k runs over (u, c)
-          tile_cgemm(Dn, Dn, 2 * Dc,
+          tile_cgemm(gl, Dn, Dn, 2 * Dc,
                      [&](int e, int k) { const int u = k >= Dc, c = k - (u ? Dc : 0);
                                          return load_c<T, double>(A, (size_t)(c * 2 + u) * S + e); },
                      [&](int k, int ep) { const int u = k >= Dc, c = k - (u ? Dc : 0);
@@ -766,13 +829,13 @@ __global__ __launch_bounds__(kWT) void k_pairs_wide(const T* state, const T* env
       const T* A = st + (size_t)j * SLOT;
       const T* Ev = evr + (size_t)(j + 1) * s2 * 2;
       for (int tp = 0; tp < 2; ++tp)
-        tile_cgemm(Dj, Dd, Dj, [&](int bb, int bp) { return load_c<T, double>(Ev, (size_t)bb * S + bp); },
+        tile_cgemm(gl, Dj, Dd, Dj, [&](int bb, int bp) { return load_c<T, double>(Ev, (size_t)bb * S + bp); },
                    [&](int bp, int dp) { return cconj(load_c<T, double>(A, (size_t)(dp * 2 + tp) * S + bp)); },
                    [&](int bb, int dp, cd v) { Tm[(size_t)(tp * S + bb) * S + dp] = v; });
       __syncthreads();
       for (int blk = 0; blk < 3; ++blk) {
         const int t = blk == 2 ? 1 : 0, tp = blk == 0 ? 0 : 1;
-        tile_cgemm(Dd, Dd, Dj, [&](int d, int bb) { return load_c<T, double>(A, (size_t)(d * 2 + t) * S + bb); },
+        tile_cgemm(gl, Dd, Dd, Dj, [&](int d, int bb) { return load_c<T, double>(A, (size_t)(d * 2 + t) * S + bb); },
                    [&](int bb, int dp) { return Tm[(size_t)(tp * S + bb) * S + dp]; },
                    [&](int d, int dp, cd v) { G[(size_t)(blk * S + d) * S + dp] = v; });
       }
