@@ -320,8 +320,7 @@ def run_grid(args):
 
             def step():
                 anomps.init_batch(b, pix)
-                for layer in range(L):
-                    anomps.apply_layer(b, thd[layer], phd[layer])
+                anomps.apply_layers(b, thd, phd)
                 anomps.pauli_pair_expect(b, pd, out)
             step()
             torch.cuda.synchronize()
@@ -411,7 +410,7 @@ def run_chisweep(args):
     from oracle import features as ofeat
     prec = anomps.PRECISIONS[args.precision]
     p, L = args.p, 7
-    B = args.batch if args.batch != 1024 else 256
+    B = args.batch
     n = p * p
     x = inputs.blob_images(B, p, 2)
     th, ph = inputs.layer_angles(L, n, 11)
