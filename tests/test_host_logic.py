@@ -81,6 +81,19 @@ def test_layers_that_keep_every_singular_value():
     assert w.layer_bytes(49, 16, 3, 4) == w.state_bytes(49, 16, 3, 4) + w.state_bytes(49, 16, 4, 4)
 
 
+def test_exact_layer_before_truncation_priced_as_qr():
+    """A layer that keeps every singular value but is followed by a truncating one is counted
+    as the QR sweep (the library applies it so); the last layer of a batch and layers followed
+    by exact ones keep the product-operator count."""
+    from paper_2607_10280_amd import workload as w
+    assert [w.next_truncates(49, 8, l, 4) for l in range(4)] == [False, False, True, False]
+    assert [w.next_truncates(49, 64, l, 7) for l in range(7)] == [False] * 5 + [True, False]
+    assert not any(w.next_truncates(49, 16, l, 4) for l in range(4))
+    assert w.layer_flops(49, 8, 2, "mpo", n_layers=4) == w.layer_flops(49, 8, 2, "qr")
+    assert w.layer_flops(49, 8, 1, "mpo", n_layers=4) == w.layer_flops(49, 8, 1, "mpo")
+    assert w.layer_flops(49, 16, 3, "mpo", n_layers=4) == w.layer_flops(49, 16, 3, "mpo")
+
+
 def test_product_operator_plan():
     """The site-by-site form of an exact layer applies exactly when the layer keeps every
     singular value; its reduced ends at 7x7, chi = 16 are the bonds whose rule dimension is
