@@ -172,20 +172,34 @@ __device__ __forceinline__ int kidx(int kc, int g) {
 // zero outside the Dl x Dr corner:
 //   column form a[u][kc] = A_u[k][l%16]  (B-operand of A_u, A-operand of A_u^T)
 //   row form    a[u][kc] = A_u[l%16][k]  (A-operand of A_u, B-operand of A_u^T),  k = kidx(kc, g)
+// load() reads all 16 x 16 entries of both slices (always inside the slot) and only notes which
+// lie in the corner; settle() zeroes the others and must run before the operands are used.  A
+// select on the loaded values at load time would make the wavefront wait for the loads right
+// there, and the fetch ahead of use would hide nothing.
 template <typename R>
 struct SiteOps {
   cx<R> a[2][4];
+  unsigned keep;  // bit kc: entry kc of this lane lies in the corner (for both slices)
   __device__ __forceinline__ void load(const R* slot, int Dl, int Dr, bool row) {
     const int l = threadIdx.x, i16 = l & 15, g = l >> 4;
+    keep = 0;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int kc = 0; kc < 4; ++kc) {
+      const int kk = kidx<R>(kc, g), c = row ? i16 : kk, e = row ? kk : i16;
+      keep |= (unsigned)(c < Dl && e < Dr) << kc;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) {
-        const int kk = kidx<R>(kc, g), c = row ? i16 : kk, e = row ? kk : i16;
+      for (int u = 0; u < 2; ++u) {
         const int idx = (c * 2 + u) * 16 + e;
-        const cx<R> v{slot[2 * idx], slot[2 * idx + 1]};
-        a[u][kc] = (c < Dl && e < Dr) ? v : cx<R>{R(0), R(0)};
+        a[u][kc] = cx<R>{slot[2 * idx], slot[2 * idx + 1]};
       }
+    }
+  }
+  __device__ __forceinline__ void settle() {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (!((keep >> kc) & 1u)) a[u][kc] = cx<R>{R(0), R(0)};
   }
 };
 
@@ -304,24 +318,38 @@ __device__ __forceinline__ void env16_image(const typename MmaReal<MODE>::type* 
       dst[2 * idx + 1] = e.im[r];
     }
   };
-  SiteOps<R> cur, nxt;
+  // The chain has one wavefront per (image, side), two per SIMD at a batch of 1024, so nothing
+  // hides a site's load latency but the chain's own lead: the operands of the next kEnvAhead
+  // sites are in flight while a site is transferred (a ring of registers, indexed statically by
+  // unrolling the loop kEnvAhead steps at a time).
+  constexpr int kEnvAhead = 3;
+  SiteOps<R> ring[kEnvAhead];
   const bool right = side != 0;
   auto fetch = [&](int t, SiteOps<R>& o) {
     const int k = right ? n - 1 - t : t;
     o.load(st + (size_t)k * SLOT, dim(k - 1), dim(k), right);
   };
   store_env(right ? n : 0);
-  fetch(0, cur);
-  for (int t = 0; t < n; ++t) {
-    if (t + 1 < n) fetch(t + 1, nxt);
-    C eo[4];
-    acc_as_b(e, eo);
-    // Left: L_{k+1} = sum_u A_u^T L_k conj(A_u) from the column forms.  Right:
-    // R_k = sum_s A_s R_{k+1} A_s^H, i.e. Y_s = R conj(A_s^T) and R_k^T = sum_s Y_s^T A_s^T: the
-    // same two products with the row forms (the row form of A_s is the column form of A_s^T).
-    e = left_transfer_t<MODE>(eo, cur.a);
-    store_env(right ? n - 1 - t : t + 1);
-    cur = nxt;
+#pragma unroll
+  for (int j = 0; j < kEnvAhead; ++j)
+    if (j < n) fetch(j, ring[j]);
+  for (int t0 = 0; t0 < n; t0 += kEnvAhead) {
+#pragma unroll
+    for (int j = 0; j < kEnvAhead; ++j) {
+      const int t = t0 + j;
+      if (t < n) {
+        C eo[4];
+        acc_as_b(e, eo);
+        // Left: L_{k+1} = sum_u A_u^T L_k conj(A_u) from the column forms.  Right:
+        // R_k = sum_s A_s R_{k+1} A_s^H, i.e. Y_s = R conj(A_s^T) and R_k^T = sum_s Y_s^T A_s^T:
+        // the same two products with the row forms (the row form of A_s is the column form of
+        // A_s^T).
+        ring[j].settle();
+        e = left_transfer_t<MODE>(eo, ring[j].a);
+        store_env(right ? n - 1 - t : t + 1);
+        if (t + kEnvAhead < n) fetch(t + kEnvAhead, ring[j]);
+      }
+    }
   }
 }
 
@@ -435,6 +463,7 @@ __device__ __forceinline__ void pairs16_image(const typename MmaReal<MODE>::type
     int nk, ns;
     successor(kind, site, nk, ns);
     if (nk >= 0) fetch(nk, ns, pb);
+    pa.s.settle();
     if (kind == 2) {
       C ac[4], xa[4];
       conj4(pa.s.a[0], ac);
