@@ -150,11 +150,29 @@ __device__ __forceinline__ void acc_as_b(const AccT<V>& c, C (&b)[4]) {
   for (int r = 0; r < 4; ++r) b[r] = C{c.re[r], c.im[r]};
 }
 
+// Sums over the 64 lanes of 16 values at once, in 17 exchanges instead of 16 x 6: at the step
+// with lane offset o the lane keeps the half of its values whose index bit matches its own lane
+// bit and adds its partner's copy of that half, so after the offsets 32, 16, 8, 4 lane l holds
+// value (l >> 2) & 15 summed over the lanes that differ from it in bits 2..5, and the offsets
+// 2 and 1 finish the sum.  Total of value e: read it from lane 4e.
 template <typename R>
-__device__ __forceinline__ R wave_sum(R v) {
+__device__ __forceinline__ R sum16_lanes(const R (&v)[16]) {
+  const int l = threadIdx.x;
+  R a8[8], a4[4], a2[2];
+  bool hi = (l >> 5) & 1;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  for (int i = 0; i < 8; ++i) a8[i] = (hi ? v[i + 8] : v[i]) + __shfl_xor(hi ? v[i] : v[i + 8], 32);
+  hi = (l >> 4) & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a4[i] = (hi ? a8[i + 4] : a8[i]) + __shfl_xor(hi ? a8[i] : a8[i + 4], 16);
+  hi = (l >> 3) & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) a2[i] = (hi ? a4[i + 2] : a4[i]) + __shfl_xor(hi ? a4[i] : a4[i + 2], 8);
+  hi = (l >> 2) & 1;
+  R s = (hi ? a2[1] : a2[0]) + __shfl_xor(hi ? a2[0] : a2[1], 4);
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 1);
+  return s;
 }
 
 // The k index that lane group g (= l/16) covers in the product's k-chunk kc.  The FP32 and bf16
@@ -527,16 +545,22 @@ __device__ __forceinline__ void pairs16_image(const typename MmaReal<MODE>::type
         e13 = C{e13.re + p13.re, e13.im + p13.im};
         e23 = C{e23.re + p23.re, e23.im + p23.im};
       }
-      d00 = wave_sum(d00);
-      d11 = wave_sum(d11);
-      d22 = wave_sum(d22);
-      d33 = wave_sum(d33);
-      e01 = C{wave_sum(e01.re), wave_sum(e01.im)};
-      e02 = C{wave_sum(e02.re), wave_sum(e02.im)};
-      e03 = C{wave_sum(e03.re), wave_sum(e03.im)};
-      e12 = C{wave_sum(e12.re), wave_sum(e12.im)};
-      e13 = C{wave_sum(e13.re), wave_sum(e13.im)};
-      e23 = C{wave_sum(e23.re), wave_sum(e23.im)};
+      {
+        const R part[16] = {d00,    d11,    d22,    d33,    e01.re, e01.im, e02.re, e02.im,
+                            e03.re, e03.im, e12.re, e12.im, e13.re, e13.im, e23.re, e23.im};
+        const R s = sum16_lanes(part);
+        auto total = [&](int e) { return __shfl(s, 4 * e); };
+        d00 = total(0);
+        d11 = total(1);
+        d22 = total(2);
+        d33 = total(3);
+        e01 = C{total(4), total(5)};
+        e02 = C{total(6), total(7)};
+        e03 = C{total(8), total(9)};
+        e12 = C{total(10), total(11)};
+        e13 = C{total(12), total(13)};
+        e23 = C{total(14), total(15)};
+      }
       // full rho (row-major 4x4): lower triangle = conjugate transpose
       const C rho[16] = {C{d00, 0}, e01, e02, e03,
                          C{e01.re, -e01.im}, C{d11, 0}, e12, e13,
