@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_VALU_TFLOPS = 78.6  # FP32 vector with packed FP32 disabled (same lane count and clock)
 PEAK_FP32_MFMA_TFLOPS = 157.3  # FP32 matrix cores (dense)
+PEAK_FP64_MFMA_TFLOPS = 78.6   # FP64 matrix cores (dense)
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # bf16 matrix cores (dense)
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0,
@@ -36,11 +38,11 @@ MEASURED_TRAFFIC = {
     # one mps_apply_layers call (all four layers): k_mpo_run_core + k_mpo_run_ends
     "layers": {"source": "paper_2607_10280_amd/csrc/layer.hip",
                "sha1": "0907698710102818f3f2e5ee101d2b7c003502cf",
-               "bytes": ((2 * 5316.0 + 167936.0) + (2 * 4975.3 + 6277.2)) * 1024},
+               "bytes": ((2 * 5316.6 + 167936.0) + (2 * 4973.6 + 6351.6)) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "51f4562a590a9821032233df6fdf399ab33755c1",
-                "bytes": (2 * (194788.5 + 232401.3) + (204801.1 + 6013.6)) * 1024},
+                "sha1": "0c90ca3ec5bb4ffedf2370956c21dc0f92de4400",
+                "bytes": (2 * (194774.7 + 231155.6) + (204826.7 + 6091.8)) * 1024},
 }
 
 
@@ -706,15 +708,22 @@ def main():
     # Roofline of the dominant kernel family.
     lay_flops = sum(workload.layer_flops(n, chi, l, n_layers=L)["total_fp64"] for l in range(L)) * B
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
-    mfma = prec == anomps.PREC_FP32 and anomps.slot_dim(n, chi, L) == 16
+    # Slot-16 measurement runs on matrix cores in every precision (FP64, FP32, or bf16 with
+    # three bf16 products per FP32 product: the split variant is priced against the bf16 peak
+    # with the algorithmic, FP32-product count); narrower slots on the vector units.
+    if anomps.slot_dim(n, chi, L) == 16:
+        meas_bound, meas_peak = "mfma", {anomps.PREC_FP64: PEAK_FP64_MFMA_TFLOPS,
+                                         anomps.PREC_FP32: PEAK_FP32_MFMA_TFLOPS,
+                                         anomps.PREC_SPLIT_BF16: PEAK_BF16_MFMA_TFLOPS}[prec]
+    else:
+        meas_bound = "alu"
+        meas_peak = PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else PEAK_FP32_VALU_TFLOPS
     cand = {
         "layers": (lay_flops, avg["layers"], "alu", PEAK_FP64_TFLOPS,
                    "FP64 VALU, per mps_apply_layers call (all L layers): gates + parity-operator "
                    "contraction with exact end carries for layers that keep every singular "
                    "value, else Jacobi SVD (nominal R-SVD count) + canonical sweep"),
-        "measure": (meas_flops, avg["measure"], "mfma" if mfma else "alu",
-                    PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else
-                    (PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_VALU_TFLOPS),
+        "measure": (meas_flops, avg["measure"], meas_bound, meas_peak,
                     "environments + pair contractions, per measurement call"),
     }
     dom = max(cand, key=lambda k: per_step[k])
