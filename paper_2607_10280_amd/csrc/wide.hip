@@ -59,6 +59,21 @@ __device__ __forceinline__ double team_sum16(double v) {
   return v;
 }
 
+// Sum over each half (8 lanes) of a DPP row: half-mirror, then the two quad swaps.
+__device__ __forceinline__ double team_sum8(double v) {
+  v += w_dpp<0x141>(v);
+  v += w_dpp<0x4E>(v);
+  v += w_dpp<0xB1>(v);
+  return v;
+}
+
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double v) {
+  static_assert(TEAM == 8 || TEAM == 16, "team of 8 or 16 lanes");
+  if constexpr (TEAM == 8) return team_sum8(v);
+  return team_sum16(v);
+}
+
 // 1/sqrt(x), x > 0: hardware estimate and two Newton steps.
 __device__ __forceinline__ double w_rsqrt(double x) {
   double r = __builtin_amdgcn_rsq(x);
@@ -272,14 +287,15 @@ __device__ __forceinline__ int rr_pos(int i, int r, int NP) {
 }
 
 // One-sided Jacobi on the N columns (rows [0, M)) of mat (leading dimension ld), FP64: per
-// round the NP/2 disjoint pairs of the round-robin tournament are spread over the 16-lane teams;
-// a team holds R rows per lane of both columns in registers, reduces |x|^2, |y|^2 and x^H y
-// with DPP, rotates when |x^H y|^2 > (M eps)^2 |x|^2 |y|^2 and writes both columns back.
+// round the NP/2 disjoint pairs of the round-robin tournament are spread over the teams of TEAM
+// lanes; a team holds R rows per lane of both columns in registers, reduces |x|^2, |y|^2 and
+// x^H y with DPP, rotates when |x^H y|^2 > (M eps)^2 |x|^2 |y|^2 and writes both columns back.
 // Stops after a sweep whose rotated pairs were all within 1e-8 of orthogonal.  On return
 // sig2[c] = |w_c|^2 and sh.tiny2 = 1e-30 |A|_F^2 (columns at or below it count as zero).
-template <int R>
+template <int R, int TEAM>
 __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
-  const int tid = threadIdx.x, team = tid / kTeam, lt = tid % kTeam;
+  constexpr int TEAMS = kWT / TEAM;
+  const int tid = threadIdx.x, team = tid / TEAM, lt = tid % TEAM;
   double f = 0.0;
   for (int idx = tid; idx < N * M; idx += kWT) {
     const cd v = mat[(size_t)(idx / M) * ld + idx % M];
@@ -293,7 +309,7 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
   for (int sweep = 0; !converged && sweep < kWideSweeps; ++sweep) {
     int rotated = 0, big = 0;
     for (int r = 0; r < NP - 1; ++r) {
-      for (int q = team; q < P; q += kTeams) {
+      for (int q = team; q < P; q += TEAMS) {
         const int ci = rr_pos(q, r, NP), cj = rr_pos(NP - 1 - q, r, NP);
         if (ci >= N || cj >= N) continue;
         cd* xc = mat + (size_t)ci * ld;
@@ -302,7 +318,7 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
         double gr = 0.0, gi = 0.0, a = 0.0, bb = 0.0;
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-          const int row = lt + t * kTeam;
+          const int row = lt + t * TEAM;
           x[t] = row < M ? xc[row] : cd{0.0, 0.0};
           y[t] = row < M ? yc[row] : cd{0.0, 0.0};
           gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
@@ -310,10 +326,10 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
           a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
           bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
         }
-        a = team_sum16(a);
-        bb = team_sum16(bb);
-        gr = team_sum16(gr);
-        gi = team_sum16(gi);
+        a = team_sum<TEAM>(a);
+        bb = team_sum<TEAM>(bb);
+        gr = team_sum<TEAM>(gr);
+        gi = team_sum<TEAM>(gi);
         const double ag2 = fma(gr, gr, gi * gi);
         const double ab = a * bb;
         if (a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
@@ -327,7 +343,7 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
           const cd e{gr * rg, -gi * rg};  // conj(g)/|g|
 #pragma unroll
           for (int t = 0; t < R; ++t) {
-            const int row = lt + t * kTeam;
+            const int row = lt + t * TEAM;
             const cd ye = cmul(e, y[t]);
             if (row < M) {
               xc[row] = cd{fma(c, x[t].re, -s * ye.re), fma(c, x[t].im, -s * ye.im)};
@@ -340,11 +356,11 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
     }
     converged = !__syncthreads_or(rotated & big);
   }
-  for (int c = team; c < N; c += kTeams) {
+  for (int c = team; c < N; c += TEAMS) {
     const cd* col = mat + (size_t)c * ld;
     double s2 = 0.0;
-    for (int row = lt; row < M; row += kTeam) s2 = fma(col[row].re, col[row].re, fma(col[row].im, col[row].im, s2));
-    s2 = team_sum16(s2);
+    for (int row = lt; row < M; row += TEAM) s2 = fma(col[row].re, col[row].re, fma(col[row].im, col[row].im, s2));
+    s2 = team_sum<TEAM>(s2);
     if (lt == 0) sh.sig2[c] = s2;
   }
   if (tid == 0) sh.tiny2 = tiny2;
@@ -352,13 +368,18 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
   return converged ? 0 : kImgNoConvergence;
 }
 
+// Teams of 8 lanes (32 column pairs at a time) up to 128 rows, of 16 lanes above: the sweep's
+// rounds are short chains of dependent steps, and more pairs in flight per image shorten them.
 __device__ int wide_jacobi(WideShared& sh, cd* mat, int ld, int M, int N) {
-  const int rows = (M + kTeam - 1) / kTeam;
-  if (rows <= 1) return wide_jacobi_r<1>(sh, mat, ld, M, N);
-  if (rows <= 2) return wide_jacobi_r<2>(sh, mat, ld, M, N);
-  if (rows <= 4) return wide_jacobi_r<4>(sh, mat, ld, M, N);
-  if (rows <= 8) return wide_jacobi_r<8>(sh, mat, ld, M, N);
-  return wide_jacobi_r<16>(sh, mat, ld, M, N);
+  if (M <= 128) {
+    const int rows = (M + 7) / 8;
+    if (rows <= 1) return wide_jacobi_r<1, 8>(sh, mat, ld, M, N);
+    if (rows <= 2) return wide_jacobi_r<2, 8>(sh, mat, ld, M, N);
+    if (rows <= 4) return wide_jacobi_r<4, 8>(sh, mat, ld, M, N);
+    if (rows <= 8) return wide_jacobi_r<8, 8>(sh, mat, ld, M, N);
+    return wide_jacobi_r<16, 8>(sh, mat, ld, M, N);
+  }
+  return wide_jacobi_r<(256 + kTeam - 1) / kTeam, kTeam>(sh, mat, ld, M, N);
 }
 
 // Right-to-left sweep: gates (mode != none) and right-canonical sites n-1..1 by Householder LQ;
