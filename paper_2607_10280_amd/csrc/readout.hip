@@ -72,13 +72,41 @@ __global__ __launch_bounds__(kRoThreads) void k_readout(const R* pauli, const R*
     qs[bi * mp + jj] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < nb * no; idx += kRoThreads) {
-    const int bi = idx / no, oo = idx - bi * no;
-    R acc = bias ? bias[o0 + oo] : (R)0;
-    const R* wr = ws + oo * mp;
-    const R* qv = qs + bi * mp;
-    for (int jj = 0; jj < m; ++jj) acc += wr[jj] * qv[jj];
-    y[(size_t)(b0 + bi) * out_dim + o0 + oo] = acc;
+  // Each lane: images 2 ip, 2 ip + 1 and outputs oq + 32 u (u < 4), so that a step of the sum
+  // reads 4 + 2 LDS values for 8 products; rows past the block's images or outputs are clamped
+  // to the last one (in bounds) and not stored.  Each sum runs over j in order, as a plain dot.
+  for (int item = tid; item < ((nb + 1) / 2) * 32; item += kRoThreads) {
+    const int ip = item / 32, oq = item % 32;
+    const R* wr[4];
+    const R* qv[2];
+    R acc[2][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wr[u] = ws + min(oq + 32 * u, no - 1) * mp;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) qv[v] = qs + min(2 * ip + v, nb - 1) * mp;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = min(oq + 32 * u, no - 1);
+        acc[v][u] = bias ? bias[o0 + o] : (R)0;
+      }
+    for (int jj = 0; jj < m; ++jj) {
+      const R q0 = qv[0][jj], q1 = qv[1][jj];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const R w = wr[u][jj];
+        acc[0][u] += w * q0;
+        acc[1][u] += w * q1;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int bi = 2 * ip + v, o = oq + 32 * u;
+        if (bi < nb && o < no) y[(size_t)(b0 + bi) * out_dim + o0 + o] = acc[v][u];
+      }
   }
 }
 
