@@ -612,8 +612,11 @@ __device__ __forceinline__ void pairs16_block(const typename MmaReal<MODE>::type
                                               int batch, typename MmaReal<MODE>::type* out) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD;
-  const int b = NXCD * (jw / (n - 1)) + xcd, i = jw % (n - 1);
+  // Start site major: every image's start site 0 first, the last sites (for neighbour pairs,
+  // those with only short partners and no carry) last, so that the launch ends on short
+  // workgroups.  Image b still runs on XCD b % NXCD.
+  const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD, groups = (batch + NXCD - 1) / NXCD;
+  const int b = NXCD * (jw % groups) + xcd, i = jw / groups;
   if (b >= batch) return;
   pairs16_image<MODE>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs,
                       m, n, chi, layers, i, out + (size_t)b * m * 15);
