@@ -38,11 +38,11 @@ MEASURED_TRAFFIC = {
     # one mps_apply_layers call (all four layers): k_mpo_run_core + k_mpo_run_ends
     "layers": {"source": "paper_2607_10280_amd/csrc/layer.hip",
                "sha1": "0907698710102818f3f2e5ee101d2b7c003502cf",
-               "bytes": ((2 * 5316.6 + 167936.0) + (2 * 4973.6 + 6351.6)) * 1024},
+               "bytes": ((2 * 5316.7 + 167936.0) + (2 * 4974.2 + 6260.0)) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "0c90ca3ec5bb4ffedf2370956c21dc0f92de4400",
-                "bytes": (2 * (194774.7 + 231155.6) + (204826.7 + 6091.8)) * 1024},
+                "sha1": "c6c9cc4b97a5bb9efc391a340bbd09b0ba75f440",
+                "bytes": (2 * (194730.2 + 439745.1) + (204825.4 + 8715.8)) * 1024},
 }
 
 
