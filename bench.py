@@ -68,12 +68,17 @@ def parse():
     ap.add_argument("--chi", type=int, default=16)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_bf16"])
     ap.add_argument("--plain-images", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager step instead of its HIP-graph replay")
-    ap.add_argument("--no-svd-compare", action="store_true",
-                    help="skip the extra timing with every layer through the SVD ladder")
+    ap.add_argument("--layers-mode", default="svd", choices=["svd", "qr", "mpo"],
+                    help="how layers that keep every singular value are applied in the timed "
+                         "step: svd = canonical sweep + Jacobi SVD ladder like every other layer "
+                         "(the method; default), qr / mpo = the exact shortcuts")
+    ap.add_argument("--no-shortcut", action="store_true",
+                    help="skip the extra timing of the exact shortcut (mpo) beside the method")
+    ap.add_argument("--no-trunc-cell", action="store_true",
+                    help="skip the extra timing of the truncating cell (chi = 8)")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "mixed", "serve", "grid", "paper", "chisweep",
                              "precision"],
@@ -90,8 +95,7 @@ def parse():
     return ap.parse_args()
 
 
-class _SkipSvd(Exception):
-    pass
+LAYER_MODES = {"qr": 0, "svd": 1, "mpo": 2}   # mps_set_exact_layers modes
 
 
 # ----------------------------------------------------------------------------- CPU baseline
@@ -108,22 +112,62 @@ def _oracle_worker(args):
     return f[0], time.perf_counter() - t0
 
 
-def cpu_baseline(x, th, ph, pairs, chi, sample):
-    """The FP64 oracle (same truncation rule and chi) on `sample` images, one process per core."""
-    cores = min(os.cpu_count() or 1, 16, sample)
-    jobs = [(x[i], th, ph, pairs, chi) for i in range(sample)]
-    t0 = time.perf_counter()
+def _warm_worker():
+    """Pool initializer: one BLAS thread, the oracle imported and run once on a tiny input, so
+    that neither process start-up nor first-call costs fall inside the timed region."""
+    _single_thread()
+    from oracle import features as ofeat
+    ofeat.truncated_features(np.full((1, 4), 0.5), np.zeros((1, 4)), np.zeros((1, 4)),
+                             np.array([[0, 1]], np.int32), 2)
+
+
+def _ready(_):
+    return os.getpid()
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, th, ph, pairs, chi, one_core=16, per_worker=8, max_workers=16):
+    """The FP64 oracle (same truncation rule and chi) on the host: `one_core` images serially in
+    one process (1-core rate), then `per_worker` images per process over a persistent pool of
+    min(os.cpu_count(), max_workers) single-threaded processes (all-core rate).  The pool is
+    started and warmed before either timer starts.  Returns (features of the all-core sample,
+    record)."""
+    workers = max(1, min(os.cpu_count() or 1, max_workers))
+    n_all = min(len(x), workers * per_worker)
+    n_one = min(len(x), one_core)
     ctx = mp.get_context("spawn")
-    with ctx.Pool(cores, initializer=_single_thread) as pool:
-        res = pool.map(_oracle_worker, jobs)
-    wall = time.perf_counter() - t0
+    with ctx.Pool(workers, initializer=_warm_worker) as pool:
+        pool.map(_ready, range(4 * workers), chunksize=1)   # every worker started and warm
+        t0 = time.perf_counter()
+        for i in range(n_one):
+            pool.apply(_oracle_worker, ((x[i], th, ph, pairs, chi),))
+        one_s = time.perf_counter() - t0
+        jobs = [(x[i], th, ph, pairs, chi) for i in range(n_all)]
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_worker, jobs, chunksize=1)
+        all_s = time.perf_counter() - t0
     feats = np.stack([r[0] for r in res])
-    per_image = np.mean([r[1] for r in res])
-    return feats, {"value": round(sample / wall, 3), "unit": "images/s", "cores": cores,
-                   "kind": "oracle",
-                   "sample": f"{sample} of the batch's images through the FP64 CPU oracle (numpy/"
-                             f"LAPACK MPS, same chi and truncation rule), one process per core; "
-                             f"{per_image:.2f} s per image per core"}
+    per_image = float(np.mean([r[1] for r in res]))
+    rec = {"value": round(n_all / all_s, 3), "unit": "images/s", "cores": workers,
+           "kind": "oracle",
+           "one_core_images_per_s": round(n_one / one_s, 3),
+           "cpu_count": os.cpu_count(), "cpu_model": _cpu_model(),
+           "sample": f"FP64 CPU oracle (numpy/LAPACK MPS, same chi and truncation rule) on the "
+                     f"batch's first images: {n_one} serially in one process (1-core rate), then "
+                     f"{n_all} over a warm pool of {workers} single-threaded processes (all-core "
+                     f"rate, {per_worker} per process); {per_image:.3f} s per image per core; "
+                     f"the pool is capped at {max_workers} processes, the GPU box's CPU share"}
+    return feats, rec
 
 
 # ----------------------------------------------------------------------------- mixed / serve
@@ -585,7 +629,7 @@ def main():
     batch = anomps.new_batch(n, chi, L, B, prec)
     stream = torch.cuda.current_stream()
 
-    def step(b=batch, pix=pix_d, out=out_d, y=y_d, events=None):
+    def step(b=batch, pix=pix_d, out=out_d, y=y_d, events=None, th_=th_d, ph_=ph_d):
         def mark(name):
             if events is not None:
                 ev = torch.cuda.Event(enable_timing=True)
@@ -594,7 +638,7 @@ def main():
         mark("start")
         anomps.init_batch(b, pix)
         mark("encode")
-        anomps.apply_layers(b, th_d, ph_d)
+        anomps.apply_layers(b, th_, ph_)
         mark("layers")
         anomps.pauli_pair_expect(b, pairs_d, out)
         mark("measure")
@@ -611,63 +655,74 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # Eager: one stream-ordered call per step function.
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    eager_ms = e0.elapsed_time(e1) / args.steps
-    eager_out = out_d.cpu().numpy()
-    eager_y = y_d.cpu().numpy()
+    def per_call(stepf, count):
+        """Average duration of each call of the step (HIP events on the launch stream)."""
+        per = {}
+        for _ in range(count):
+            evs = []
+            stepf(events=evs)
+            torch.cuda.synchronize()
+            for (_, a), (name, b) in zip(evs[:-1], evs[1:]):
+                per.setdefault(name, []).append(a.elapsed_time(b))
+        return {k: float(np.mean(v)) for k, v in per.items()}
 
-    # The same step captured once as a HIP graph and replayed (no host launch gaps between the
-    # step's kernels; the library's second stream for layer runs joins the capture through its
-    # fork/join events).  Its outputs must equal the eager step's bit for bit.
-    graph = None
-    if not args.no_graph:
-        cs = torch.cuda.Stream()
-        cs.wait_stream(stream)
+    def timed(mode_name, stepf, use_graph):
+        """Warm-up, eager timing, then (unless disabled) a HIP-graph capture of the same step
+        and its timed replays; returns a dict of timings and the outputs of the timed run."""
+        anomps.set_exact_layers(LAYER_MODES[mode_name])
+        for _ in range(args.warmup):
+            stepf()
         torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=cs):
-            step()
-        graph.replay()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            stepf()
+        e1.record(stream)
         torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        if graph is not None:
+        eager_ms = e0.elapsed_time(e1) / args.steps
+        eager_out, eager_y = out_d.cpu().numpy(), y_d.cpu().numpy()
+        # The same step captured once as a HIP graph and replayed (no host launch gaps between
+        # the step's kernels; the library's second stream for layer runs joins the capture
+        # through its fork/join events).  Its outputs must equal the eager step's bit for bit.
+        graph = None
+        if use_graph:
+            cs = torch.cuda.Stream()
+            cs.wait_stream(stream)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=cs):
+                stepf()
             graph.replay()
-        else:
-            step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    status = batch.status.cpu().numpy()
-    gpu_out = out_d.cpu().numpy()
-    graph_same = graph is None or (np.array_equal(gpu_out, eager_out)
-                                   and np.array_equal(y_d.cpu().numpy(), eager_y))
-
-    # Per-call durations (HIP events on the launch stream), same steps again.
-    per = {}
-    for _ in range(args.steps):
-        evs = []
-        step(events=evs)
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            if graph is not None:
+                graph.replay()
+            else:
+                stepf()
+        e1.record(stream)
         torch.cuda.synchronize()
-        for (_, a), (name, b) in zip(evs[:-1], evs[1:]):
-            per.setdefault(name, []).append(a.elapsed_time(b))
-    avg = {k: float(np.mean(v)) for k, v in per.items()}   # ms per call
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / args.steps
+        outs = out_d.cpu().numpy()
+        same = graph is None or (np.array_equal(outs, eager_out)
+                                 and np.array_equal(y_d.cpu().numpy(), eager_y))
+        avg = per_call(stepf, args.steps)
+        del graph
+        return {"ms": ms, "eager_ms": eager_ms, "wall": wall, "graph_same": bool(same),
+                "graph": use_graph, "avg": avg, "out": outs,
+                "status": batch.status.cpu().numpy()}
+
+    mode = args.layers_mode
+    head = timed(mode, step, not args.no_graph)
+    avg = head["avg"]
     per_step = {"encode": avg["encode"], "layers": avg["layers"], "measure": avg["measure"],
                 "readout": avg["readout"]}
+    gpu_out = head["out"]
 
-    # Plain method: one image per call, serial, on the same GPU.
+    # Plain method: one image per call, serial, on the same GPU (same layer mode).
     plain = anomps.new_batch(n, chi, L, 1, prec)
     lat = []
     o1 = torch.empty((1, m, 15), dtype=real, device=dev)
@@ -682,35 +737,27 @@ def main():
             lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat)
 
-    # The same batch with every layer through the canonical sweep + Jacobi SVD ladder (by
-    # default a layer that keeps every singular value is applied site by site as the parity
-    # product operator).
-    anomps.set_exact_layers(anomps.EXACT_SVD)
-    try:
-        if args.no_svd_compare:
-            raise _SkipSvd
-        step()
-        torch.cuda.synchronize()
-        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s0.record()
-        for _ in range(args.steps):
-            step()
-        s1.record()
-        torch.cuda.synchronize()
-        svd_ms = s0.elapsed_time(s1) / args.steps
-        svd_err = float(np.abs(out_d.cpu().numpy().astype(np.float64) - gpu_out).max())
-    except _SkipSvd:
-        svd_ms = svd_err = None
-    finally:
-        anomps.set_exact_layers(anomps.EXACT_MPO)
-    exact = [l for l in range(L) if workload.layer_keeps_all(n, chi, l)]
+    def layer_roofline(n_, chi_, L_, B_, lay_ms, mode_name):
+        """k_layer family priced against the FP64 vector peak with the algorithmic count of
+        workload.layer_flops (nominal R-SVD count per truncating two-site split + Householder
+        canonical sweep + contractions), per launch = one layer of the whole batch."""
+        fl = sum(workload.layer_flops(n_, chi_, l, mode=mode_name, n_layers=L_)["total_fp64"]
+                 for l in range(L_)) * B_
+        ach = fl / (lay_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                "traffic": None, "kernel": "k_layer",
+                "what": f"FP64 VALU, one mps_apply_layers call = {L_} k_layer launches (one per "
+                        f"layer, one wavefront per image): canonical sweep + CNOT ladder with "
+                        f"Jacobi SVD of every two-site matrix",
+                "flops_per_launch": fl / L_, "launches": L_,
+                "avg_launch_ms": round(lay_ms / L_, 4),
+                "algorithmic_bytes_per_launch": round(
+                    sum(workload.layer_bytes(n_, chi_, l, 8 if prec == anomps.PREC_FP64 else 4,
+                                             mode=mode_name) for l in range(L_)) * B_ / L_)}
 
-    # Roofline of the dominant kernel family.
-    lay_flops = sum(workload.layer_flops(n, chi, l, n_layers=L)["total_fp64"] for l in range(L)) * B
+    # Measurement call (k_env16 + k_pairs16 at slot 16).
     meas_flops = (workload.env_flops(n, chi, L) + workload.pair_flops(n, chi, L, pairs)) * B
-    # Slot-16 measurement runs on matrix cores in every precision (FP64, FP32, or bf16 with
-    # three bf16 products per FP32 product: the split variant is priced against the bf16 peak
-    # with the algorithmic, FP32-product count); narrower slots on the vector units.
     if anomps.slot_dim(n, chi, L) == 16:
         meas_bound, meas_peak = "mfma", {anomps.PREC_FP64: PEAK_FP64_MFMA_TFLOPS,
                                          anomps.PREC_FP32: PEAK_FP32_MFMA_TFLOPS,
@@ -718,63 +765,98 @@ def main():
     else:
         meas_bound = "alu"
         meas_peak = PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else PEAK_FP32_VALU_TFLOPS
-    cand = {
-        "layers": (lay_flops, avg["layers"], "alu", PEAK_FP64_TFLOPS,
-                   "FP64 VALU, per mps_apply_layers call (all L layers): gates + parity-operator "
-                   "contraction with exact end carries for layers that keep every singular "
-                   "value, else Jacobi SVD (nominal R-SVD count) + canonical sweep"),
-        "measure": (meas_flops, avg["measure"], meas_bound, meas_peak,
-                    "environments + pair contractions, per measurement call"),
-    }
-    dom = max(cand, key=lambda k: per_step[k])
-    fl, dur_ms, bound, peak, what = cand[dom]
-    achieved = fl / (dur_ms * 1e-3) / 1e12
-    traffic = _measured_traffic(dom)
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "kernel": dom, "what": what, "flops_per_launch": fl,
-                "avg_launch_ms": round(dur_ms, 4)}
-    if dom == "layers":
-        alg = sum(workload.layer_bytes(n, chi, l, 8 if prec == anomps.PREC_FP64 else 4)
-                  for l in range(L)) * B
-        roofline["algorithmic_bytes_per_launch"] = round(alg)
+    ach_m = meas_flops / (per_step["measure"] * 1e-3) / 1e12
+    traffic_m = _measured_traffic("measure")
+    roof_measure = {"bound": meas_bound, "achieved": round(ach_m, 3), "peak": meas_peak,
+                    "unit": "TFLOP/s", "frac": round(ach_m / meas_peak, 4),
+                    "traffic": None if traffic_m is None else round(traffic_m),
+                    "kernel": "k_env16+k_pairs16",
+                    "what": "environments + pair contractions, per measurement call",
+                    "flops_per_launch": meas_flops, "avg_launch_ms": round(per_step["measure"], 4)}
+    if mode == "mpo":
+        lay_fl = sum(workload.layer_flops(n, chi, l, n_layers=L)["total_fp64"] for l in range(L)) * B
+        ach_l = lay_fl / (per_step["layers"] * 1e-3) / 1e12
+        roof_layers = {"bound": "alu", "achieved": round(ach_l, 3), "peak": PEAK_FP64_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(ach_l / PEAK_FP64_TFLOPS, 4),
+                       "traffic": None, "kernel": "k_mpo_run_core+k_mpo_run_ends",
+                       "flops_per_launch": lay_fl, "avg_launch_ms": round(per_step["layers"], 4)}
+    else:
+        roof_layers = layer_roofline(n, chi, L, B, per_step["layers"], mode)
+        traffic_l = _measured_traffic("layers_" + mode)
+        if traffic_l is not None:
+            roof_layers["traffic"] = round(traffic_l / L)
+    dom = "layers" if per_step["layers"] >= per_step["measure"] else "measure"
+    roofline = roof_layers if dom == "layers" else roof_measure
 
     result = {
         "metric": "Pauli-feature images/sec, 49q L=4 chi=16, batched vs plain; p99 latency; max abs err",
-        "value": round(args.steps * B / (ms_per_step * args.steps * 1e-3), 1),
+        "value": round(B / (head["ms"] * 1e-3), 1),
         "unit": "images/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "timing": {"mode": "eager" if graph is None else "hip_graph",
-                   "eager_ms_per_step": round(eager_ms, 4),
-                   "eager_images_per_s": round(B / (eager_ms * 1e-3), 1),
-                   "graph_identical_to_eager": bool(graph_same)},
+        "ms_per_step": round(head["ms"], 4),
+        "timing": {"mode": "hip_graph" if head["graph"] else "eager",
+                   "eager_ms_per_step": round(head["eager_ms"], 4),
+                   "eager_images_per_s": round(B / (head["eager_ms"] * 1e-3), 1),
+                   "graph_identical_to_eager": head["graph_same"]},
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {anomps.PREC_FP32: "c64+f64svd", anomps.PREC_FP64: "f64",
                   anomps.PREC_SPLIT_BF16: "c64(split-bf16 mfma)+f64svd"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{p}x{p} images ({n} qubits), Gaussian blobs, L={L}, chi={chi}, "
                                f"{m} H+V pairs x 15 Paulis, readout {m}->{out_dim}",
-                   "global_batch": B, "precision": args.precision},
-        "wall_s": round(wall, 3),
+                   "global_batch": B, "precision": args.precision,
+                   "layers": {"svd": "canonical sweep + CNOT ladder, FP64 Jacobi SVD of every "
+                                     "two-site matrix (the method as stated)",
+                              "qr": "exact Householder splits where nothing is discarded",
+                              "mpo": "exact parity-operator contraction where nothing is "
+                                     "discarded (shortcut)"}[mode]},
+        "wall_s": round(head["wall"], 3),
         "per_step_ms": {k: round(v, 4) for k, v in per_step.items()},
         "plain": {"images_per_s": round(1e3 / float(np.mean(lat)), 1),
                   "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
                   "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
                   "images": int(len(lat))},
-        "batched_latency_ms": round(ms_per_step, 4),
-        "status_nonzero": int(np.count_nonzero(status)),
+        "batched_latency_ms": round(head["ms"], 4),
+        "status_nonzero": int(np.count_nonzero(head["status"])),
         "roofline": roofline,
-        "exact_layers": {"site_local_layers": exact, "svd_every_layer": None if svd_ms is None else {
-            "images_per_s": round(B / (svd_ms * 1e-3), 1), "ms_per_step": round(svd_ms, 4),
-            "max_abs_diff_vs_default": svd_err}},
+        "roofline_layers": roof_layers,
+        "roofline_measure": roof_measure,
     }
+
+    if mode != "mpo" and not args.no_shortcut:
+        # The same batch with the exact shortcut for layers that keep every singular value
+        # (chi >= 2^L: nothing is discarded, so the parity product operator gives the same
+        # state without any SVD).  Reported beside the method, never as its value.
+        sc = timed("mpo", step, not args.no_graph)
+        result["exact_shortcut"] = {
+            "layers": "parity product operator (site-local, exact) for every layer that keeps "
+                      "all singular values; Jacobi SVD ladder elsewhere",
+            "images_per_s": round(B / (sc["ms"] * 1e-3), 1), "ms_per_step": round(sc["ms"], 4),
+            "per_step_ms": {k: round(v, 4) for k, v in sc["avg"].items()},
+            "graph_identical_to_eager": sc["graph_same"],
+            "max_abs_diff_vs_value": float(np.abs(sc["out"].astype(np.float64) - gpu_out).max())}
+
+    if not args.no_trunc_cell and (p, L, chi) == (7, 4, 16):
+        # A truncating cell of the same grid (chi = 8 < 2^L): the method with real truncation.
+        tchi = 8
+        tb = anomps.new_batch(n, tchi, L, B, prec)
+        tstep = lambda events=None: step(b=tb, events=events)  # noqa: E731
+        tc = timed(mode, tstep, False)
+        result["truncating_cell"] = {
+            "config": f"{p}x{p}, L={L}, chi={tchi}, batch {B}", "layers_mode": mode,
+            "images_per_s": round(B / (tc["ms"] * 1e-3), 1), "ms_per_step": round(tc["ms"], 4),
+            "per_step_ms": {k: round(v, 4) for k, v in tc["avg"].items()},
+            "status_nonzero": int(np.count_nonzero(tb.status.cpu().numpy())),
+            "roofline_layers": layer_roofline(n, tchi, L, B, tc["avg"]["layers"], mode)}
+        del tb
+    anomps.set_exact_layers(LAYER_MODES[mode])
+
     if not args.no_cpu_baseline:
-        ref, cpu = cpu_baseline(x, th, ph, pairs, chi, min(args.cpu_sample, B))
+        ref, cpu = cpu_baseline(x, th, ph, pairs, chi)
         err = np.abs(gpu_out[: len(ref)].astype(np.float64) - ref)
         result["max_abs_err"] = float(err.max())
         result["mae"] = float(err.mean())
+        result["oracle_images_checked"] = int(len(ref))
         result["cpu_baseline"] = cpu
     print(json.dumps(result))
 

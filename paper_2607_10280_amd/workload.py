@@ -72,10 +72,12 @@ def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo", n_layers: int |
     first full sites.  mode "qr" (such a layer in one sweep): gate the neighbour, then split
     each bond exactly -- through two Householder blocks of the centre when D = 2 D_old (no
     two-site matrix), else contract Theta' and split it by Householder QR (or not at all when D
-    equals its row count).  Otherwise, and for mode "svd": canonical sweep (gate + SVD of each
-    site's D_{k-1} x 2D_k matrix + absorbing V Sigma into the left neighbour), then the ladder
-    (two-site contraction, SVD, U^H Theta' for the new centre).  With n_layers given, mode
-    "mpo" counts a layer followed by a truncating one as mode "qr", as the library runs it."""
+    equals its row count).  Otherwise, and for mode "svd": canonical sweep (gate + LQ of each
+    site's D_{k-1} x 2D_k matrix -- it needs only orthonormal rows, priced as Householder QR of
+    the conjugate transpose with Q formed -- + absorbing L into the left neighbour), then the
+    ladder (two-site contraction, SVD, U^H Theta' for the new centre).  With n_layers given,
+    mode "mpo" counts a layer followed by a truncating one as mode "qr", as the library runs
+    it."""
     if mode == "mpo" and n_layers is not None and next_truncates(n, chi, layer, n_layers):
         mode = "qr"
     d_old = lambda k: bond(n, chi, layer, k)
@@ -111,17 +113,19 @@ def layer_flops(n: int, chi: int, layer: int, mode: str = "mpo", n_layers: int |
                 if d != rows:
                     qr += householder_qr_flops(rows, cols)
         return {"qr_fp64": qr, "svd_fp64": 0.0, "other_fp64": other, "total_fp64": qr + other}
-    svd = other = 0.0
+    svd = qr = other = 0.0
     for k in range(n - 1, 0, -1):
+        # orthonormal rows of site k (D_{k-1} x 2 D_k): the LQ factorisation it needs, i.e.
+        # Householder QR of its conjugate transpose with Q formed; L into site k-1
         dl, dr = d_old(k - 1), d_old(k)
-        svd += svd_flops(2 * dr, dl)
-        other += CMAC * (dl * dl * 2 * dr + 2 * d_old(k - 2) * dl * dl + 4 * dl * dr)
+        qr += householder_qr_flops(2 * dr, dl)
+        other += CMAC * (4 * dl * dr + 2 * d_old(k - 2) * dl * dl)
     other += CMAC * 4 * d_old(0)
     for k in range(n - 1):
         dl, dc, dr, d = d_new(k - 1), d_old(k), d_old(k + 1), d_new(k)
         svd += svd_flops(2 * dl, 2 * dr)
         other += CMAC * (2 * dl * dc * 2 * dr + 2 * d * dl * dc + d * 2 * dr * 2 * dc)
-    return {"svd_fp64": svd, "other_fp64": other, "total_fp64": svd + other}
+    return {"qr_fp64": qr, "svd_fp64": svd, "other_fp64": other, "total_fp64": svd + qr + other}
 
 
 def env_flops(n: int, chi: int, layers: int) -> float:
