@@ -247,6 +247,25 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
                           hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mps_pauli_pair_expect with the environments kept in
+ * a fixed scratch array of the library instead of b->env (which is ignored and may be NULL).
+ * The array holds MPS_NOALLOC_SCRATCH_BYTES on every device the library runs on (its own copy
+ * per device, held until the process ends); the call allocates nothing and calls no allocating
+ * routine.  Results are those of mps_pauli_pair_expect on the same batch.
+ * Errors: as mps_pauli_pair_expect; MPS_ERR_CAPACITY when the environments
+ *   (2 (n_sites+1) S^2 complex values per image, S = mps_slot_dim) exceed the scratch;
+ *   MPS_ERR_UNSUPPORTED for slots wider than 16.
+ * Every call on a device shares that device's scratch and it keeps the last call's contents
+ * (nothing in it needs to start at zero: each call writes every environment before reading
+ * it).  Calls that overlap on one device -- on different streams, or from different threads --
+ * race on the scratch: serialise them.
+ */
+#define MPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mps_pauli_pair_expect_noalloc(mps_batch* b, const int32_t* pairs, int32_t m, void* out,
+                                  hipStream_t stream);
+
+/*
  * Pauli-basis coefficients of the adaptive observables (§II-A, Eq. (4)):
  *   H_q[j][j] = D[q][j]; for the upper positions (0,1),(0,2),(0,3),(1,2),(1,3),(2,3), in this
  *   order, H_q[j][k] = A[q][idx] + i B[q][idx] and H_q[k][j] = conj; basis |s_i s_j>.

@@ -96,6 +96,9 @@ EXPORTS = {
     "mps_validate_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mps_pauli_pair_expect": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p,
                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "mps_pauli_pair_expect_noalloc": (ctypes.c_int, [ctypes.POINTER(MpsBatch), ctypes.c_void_p,
+                                                     ctypes.c_int32, ctypes.c_void_p,
+                                                     ctypes.c_void_p]),
     "mps_ano_coeffs": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p,
                                                              ctypes.c_int32, ctypes.c_void_p]),
     "mps_ano_readout": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 3 +
@@ -242,6 +245,17 @@ def pauli_pair_expect(b: Batch, pairs_dev, out, stream=None) -> None:
     m = 0 if pairs_dev is None else pairs_dev.shape[0]
     _check(lib().mps_pauli_pair_expect(ctypes.byref(b.desc), _ptr(pairs_dev), m, _ptr(out),
                                        _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def pauli_pair_expect_noalloc(b: Batch, pairs_dev, out, stream=None) -> None:
+    """mps_pauli_pair_expect with the environments in the library's fixed scratch array (no
+    allocation; b.env is not used).  Calls that overlap on one device race on the scratch."""
+    m = 0 if pairs_dev is None else pairs_dev.shape[0]
+    _check(lib().mps_pauli_pair_expect_noalloc(ctypes.byref(b.desc), _ptr(pairs_dev), m, _ptr(out),
+                                               _stream(stream)))
 
 
 def ano_coeffs(A, B, D, coeff, stream=None) -> None:

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -115,6 +116,79 @@ int check_plan(const mps_request* reqs, const mps_mixed_plan* plan) {
   return MPS_OK;
 }
 
+// Environments [batch][2][n+1][S][S]; wide slots (S > kMaxBond) append a 256-byte aligned FP64
+// workspace of wide_workspace_bytes(S) per image, used by the layer and measurement kernels.
+size_t env_part_bytes(int n, int S, int batch, int prec) {
+  const size_t e = (size_t)batch * 2 * (n + 1) * S * S * 2 * real_size(prec);
+  return S > kMaxBond ? (e + 255) / 256 * 256 : e;
+}
+
+double* wide_ws(const mps_batch* b, int S) {
+  return (double*)((char*)b->env + env_part_bytes(b->n_sites, S, b->batch, b->precision));
+}
+
+// ---- scratch of the allocation-free measurement (mps_pauli_pair_expect_noalloc)
+// A fixed device array that holds the environments of one call.  Every device the library runs
+// on gets its own copy (at its own address) when the code object is loaded there, kept until
+// the process ends.  In host code `scratch` only names the symbol: its device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) unsigned char scratch[MPS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int noalloc_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(MPS_ERR_UNSUPPORTED, "device %d outside the %d devices this build tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(MPS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return MPS_OK;
+}
+
+// Environments and pair expectations of a batch into `env` (the caller's buffer, or the
+// allocation-free entry point's scratch).
+int measure(mps_batch* b, void* env, const int32_t* pairs, int32_t m, void* out,
+            hipStream_t stream) {
+  if (m < 0) return fail(MPS_ERR_INVALID_ARG, "m=%d < 0", m);
+  if (m > 0 && (!pairs || !out)) return fail(MPS_ERR_INVALID_ARG, "pairs/out is NULL");
+  const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
+  const int L = b->layers_done;
+  hipError_t e;
+  if (S > kMaxBond) {
+    double* ws = (double*)((char*)env + env_part_bytes(b->n_sites, S, b->batch, b->precision));
+    if (b->precision == MPS_PREC_FP64)
+      e = launch_measure_wide<double>((const double*)b->state, (double*)env, ws, pairs, m,
+                                      b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
+    else
+      e = launch_measure_wide<float>((const float*)b->state, (float*)env, ws, pairs, m,
+                                     b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
+  } else if (S == 16) {
+    e = launch_measure16(b->state, env, pairs, m, b->n_sites, b->chi, L, b->batch, out,
+                         b->precision, stream);
+  } else if (b->precision == MPS_PREC_FP64) {
+    e = launch_envs<double, double>((const double*)b->state, (double*)env, b->n_sites, b->chi, S, L, b->batch, stream);
+    if (e == hipSuccess)
+      e = launch_pairs<double, double>((const double*)b->state, (const double*)env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
+  } else {
+    e = launch_envs<float, float>((const float*)b->state, (float*)env, b->n_sites, b->chi, S, L, b->batch, stream);
+    if (e == hipSuccess)
+      e = launch_pairs<float, float>((const float*)b->state, (const float*)env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
+  }
+  if (e != hipSuccess) return check_hip(e, "measurement launch");
+  return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -133,17 +207,6 @@ size_t mps_state_bytes(int32_t n, int32_t chi, int32_t layers, int32_t batch, in
   if (check_shape(n, chi, layers, batch, prec)) return 0;
   const size_t S = slot_bucket(n, chi, layers);
   return (size_t)batch * n * 2 * S * S * 2 * real_size(prec);
-}
-
-// Environments [batch][2][n+1][S][S]; wide slots (S > kMaxBond) append a 256-byte aligned FP64
-// workspace of wide_workspace_bytes(S) per image, used by the layer and measurement kernels.
-size_t env_part_bytes(int n, int S, int batch, int prec) {
-  const size_t e = (size_t)batch * 2 * (n + 1) * S * S * 2 * real_size(prec);
-  return S > kMaxBond ? (e + 255) / 256 * 256 : e;
-}
-
-double* wide_ws(const mps_batch* b, int S) {
-  return (double*)((char*)b->env + env_part_bytes(b->n_sites, S, b->batch, b->precision));
 }
 
 size_t mps_env_bytes(int32_t n, int32_t chi, int32_t layers, int32_t batch, int32_t prec) {
@@ -280,32 +343,25 @@ int mps_pauli_pair_expect(mps_batch* b, const int32_t* pairs, int32_t m, void* o
   int rc = check_batch(b);
   if (rc) return rc;
   if (!b->env) return fail(MPS_ERR_INVALID_ARG, "env is NULL");
-  if (m < 0) return fail(MPS_ERR_INVALID_ARG, "m=%d < 0", m);
-  if (m > 0 && (!pairs || !out)) return fail(MPS_ERR_INVALID_ARG, "pairs/out is NULL");
+  return measure(b, b->env, pairs, m, out, stream);
+}
+
+int mps_pauli_pair_expect_noalloc(mps_batch* b, const int32_t* pairs, int32_t m, void* out,
+                                  hipStream_t stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
   const int S = slot_bucket(b->n_sites, b->chi, b->n_layers);
-  const int L = b->layers_done;
-  hipError_t e;
-  if (S > kMaxBond) {
-    if (b->precision == MPS_PREC_FP64)
-      e = launch_measure_wide<double>((const double*)b->state, (double*)b->env, wide_ws(b, S), pairs,
-                                      m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
-    else
-      e = launch_measure_wide<float>((const float*)b->state, (float*)b->env, wide_ws(b, S), pairs,
-                                     m, b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
-  } else if (S == 16) {
-    e = launch_measure16(b->state, b->env, pairs, m, b->n_sites, b->chi, L, b->batch, out,
-                         b->precision, stream);
-  } else if (b->precision == MPS_PREC_FP64) {
-    e = launch_envs<double, double>((const double*)b->state, (double*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
-    if (e == hipSuccess)
-      e = launch_pairs<double, double>((const double*)b->state, (const double*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (double*)out, stream);
-  } else {
-    e = launch_envs<float, float>((const float*)b->state, (float*)b->env, b->n_sites, b->chi, S, L, b->batch, stream);
-    if (e == hipSuccess)
-      e = launch_pairs<float, float>((const float*)b->state, (const float*)b->env, pairs, m, b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
-  }
-  if (e != hipSuccess) return check_hip(e, "measurement launch");
-  return ok();
+  if (S > kMaxBond)
+    return fail(MPS_ERR_UNSUPPORTED, "slot %d: the allocation-free measurement takes slots up to %d",
+                S, kMaxBond);
+  const size_t need = env_part_bytes(b->n_sites, S, b->batch, b->precision);
+  if (need > MPS_NOALLOC_SCRATCH_BYTES)
+    return fail(MPS_ERR_CAPACITY, "environments need %zu bytes, more than the %zu-byte scratch",
+                need, (size_t)MPS_NOALLOC_SCRATCH_BYTES);
+  void* env = nullptr;
+  rc = noalloc_scratch(&env);
+  if (rc) return rc;
+  return measure(b, env, pairs, m, out, stream);
 }
 
 int mps_ano_coeffs(const void* A, const void* B, const void* D, int32_t m, void* coeff,
