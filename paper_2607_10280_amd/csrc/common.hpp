@@ -100,6 +100,60 @@ __device__ __forceinline__ void store_c(T* p, size_t idx, cx<R> v) {
   p[2 * idx + 1] = static_cast<T>(v.im);
 }
 
+// Cross-lane move of an FP64 value inside a DPP row (CTRL = row_mirror, row_half_mirror or a
+// quad permutation, which always read a lane of the same row): two 32-bit moves that write every
+// lane, so no old value has to be set up first.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// One-sided (Hestenes) Jacobi rotation of a column pair with |x|^2 = a, |y|^2 = b and
+// x^H y = g (|g|^2 = ag2):
+//   x' = c x - sig y,   y' = conj(sig) x + c y,   sig = c tau conj(g),
+// with tau = sign(d) / (|d| + sqrt(d^2 + |g|^2)), d = (b - a)/2, the root of
+// tau^2 |g|^2 + 2 d tau - 1 = 0 of smaller magnitude (the rotation by less than pi/4), which
+// makes x'^H y' = 0; c = 1/sqrt(1 + tau^2 |g|^2).  The update is unitary whenever
+// c^2 + |sig|^2 = 1, whatever tau is, so tau comes from the hardware estimates of 1/sqrt and
+// 1/x (relative error ~2^-22: the pair is then orthogonal to that fraction of |g|, which the
+// next sweep removes) and only c is refined to full precision by two Newton steps.
+struct JacobiRot {
+  double c, sr, si;  // sig = sr + i si
+};
+__device__ __forceinline__ JacobiRot jacobi_rot(double a, double b, double gr, double gi,
+                                                double ag2) {
+  const double d = 0.5 * (b - a);
+  const double w = fma(d, d, ag2);
+  const double q = w * __builtin_amdgcn_rsq(w);
+  const double tau = copysign(__builtin_amdgcn_rcp(fabs(d) + q), d);
+  const double u = fma(tau * tau, ag2, 1.0);
+  const double h = 0.5 * u;
+  double c = __builtin_amdgcn_rsq(u);
+  c = c * fma(-h * c, c, 1.5);
+  c = c * fma(-h * c, c, 1.5);
+  const double ct = c * tau;
+  return {c, ct * gr, -ct * gi};
+}
+// 1/x for finite x != 0: hardware estimate and two Newton steps (within an ulp or so).
+__device__ __forceinline__ double rcp_full(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// The rotated pair of one row.
+__device__ __forceinline__ void jacobi_apply(const JacobiRot& j, cd& x, cd& y) {
+  const cd x0 = x;
+  x.re = fma(j.c, x0.re, fma(-j.sr, y.re, j.si * y.im));
+  x.im = fma(j.c, x0.im, fma(-j.sr, y.im, -j.si * y.re));
+  const double yr = fma(j.sr, x0.re, fma(j.si, x0.im, j.c * y.re));
+  y.im = fma(j.sr, x0.im, fma(-j.si, x0.re, j.c * y.im));
+  y.re = yr;
+}
+
 // Per-image status flags (mirror of the public enum).
 constexpr int kImgNonfinite = 1;
 constexpr int kImgNoConvergence = 2;

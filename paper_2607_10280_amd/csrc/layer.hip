@@ -7,6 +7,7 @@
 // the current bond are staged in LDS in FP64 and every factorisation runs in FP64.
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -18,10 +19,15 @@ namespace anomps {
 constexpr int kLayerThreads = 64;
 constexpr int kMaxSweeps = 30;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+// Orders LDS accesses across the lanes of a one-wavefront workgroup: waits for the wave's own
+// LDS operations and keeps the compiler from moving memory accesses across, but leaves its
+// global loads in flight (a __syncthreads fences global memory too, i.e. waits for every
+// outstanding load and store, which would undo the prefetches of the next site tensor).  A
+// wavefront's LDS operations execute in issue order, so this is all the ordering its lanes
+// need among themselves.
+__device__ __forceinline__ void wave_sync() {
+  static_assert(kLayerThreads == 64, "one wavefront per workgroup");
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
 // ------------------------------------------------------------------------------- encode
@@ -60,10 +66,35 @@ struct LayerShared {
   cx<T> tb[2 * S * SP];       // neighbour tensor [c][t][b] at (c*2+t)*SP + b
   cd uq[2 * S * SP];          // U [r][j] at r*SP + j (ladder) or V*Sigma [j][a] at j*SP + a (sweep)
   double sig2[2 * S];
+  double isig[2 * S];         // 1/|w_c| of the column of rank j (0 for a negligible column)
   int rank[2 * S];            // columns in descending singular-value order
   double red[kLayerThreads / 64];
   double tiny2;               // negligible-column threshold of the last decomposition
 };
+
+
+// Sum over an aligned team of T lanes (T <= 16); every lane gets the bitwise-same result
+// (each step adds a lane's value to its mirror image, so all lanes add the same operands).
+template <int T>
+__device__ __forceinline__ double team_sum(double v) {
+  if constexpr (T >= 16) v += dpp_mov_d<0x140>(v);  // row_mirror
+  if constexpr (T >= 8) v += dpp_mov_d<0x141>(v);   // row_half_mirror
+  if constexpr (T >= 4) v += dpp_mov_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (T >= 2) v += dpp_mov_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  return v;
+}
+
+// Sum over the wavefront, the same value in every lane: the four DPP rows are summed inside
+// (team_sum), and their sums are read as scalars and added in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = team_sum<16>(v);
+  auto row = [&](int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+  };
+  return (row(0) + row(16)) + (row(32) + row(48));
+}
 
 // Sum over the workgroup (kLayerThreads lanes); every lane gets the same value.
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -78,25 +109,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Cross-lane moves inside a 16-lane row (DPP): mirror, half-mirror, quad swaps.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over an aligned team of T lanes (T <= 16); every lane gets the bitwise-same result
-// (each step adds a lane's value to its mirror image, so all lanes add the same operands).
-template <int T>
-__device__ __forceinline__ double team_sum(double v) {
-  if constexpr (T >= 16) v += dpp_d<0x140>(v);  // row_mirror
-  if constexpr (T >= 8) v += dpp_d<0x141>(v);   // row_half_mirror
-  if constexpr (T >= 4) v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
-  if constexpr (T >= 2) v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
-  return v;
-}
-
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps (full FP64 precision).
 __device__ __forceinline__ double rsqrt_full(double x) {
   double r = __builtin_amdgcn_rsq(x);
@@ -104,11 +116,6 @@ __device__ __forceinline__ double rsqrt_full(double x) {
   r = r * fma(-h * r, r, 1.5);
   r = r * fma(-h * r, r, 1.5);
   return r;
-}
-// 1/x for x >= 1 to ~2^-46 (used only for the rotation angle, which need not be exact).
-__device__ __forceinline__ double rcp_fast(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  return fma(r, fma(-x, r, 1.0), r);
 }
 
 // Division by a runtime divisor that is usually a power of two (bond dimensions of the
@@ -150,7 +157,7 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
 // tol = M eps; columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2 count as numerically zero.
 // On return sig2[c] = |w_c|^2 for c < N.  Returns kImgNoConvergence if the sweep limit hit.
 template <int S, typename T, int NP, int R>
-__device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
+__device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int P = NP / 2;
   constexpr int TM = (kLayerThreads / P) < 16 ? kLayerThreads / P : 16;
@@ -169,6 +176,7 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
   if (tid == 0) sh.tiny2 = tiny2;
   const double tol = (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
+  constexpr double kBig = std::is_same<T, float>::value ? 1e-8 : 1e-16;
   bool converged = (N < 2);
   int sweep = 0;
   for (; !converged && sweep < kMaxSweeps; ++sweep) {
@@ -200,47 +208,47 @@ __device__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
       const double ab = a * bb;
       if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
         rotated = 1;
-        big |= ag2 > 1e-16 * ab;
-        const double rg = rsqrt_full(ag2);                 // 1/|g|
-        const double zeta = (bb - a) * 0.5 * rg;
-        const double w = fma(zeta, zeta, 1.0);
-        double rw = __builtin_amdgcn_rsq(w);
-        rw = rw * fma(-0.5 * w * rw, rw, 1.5);
-        const double t = copysign(rcp_fast(fabs(zeta) + w * rw), zeta);
-        const double c = rsqrt_full(fma(t, t, 1.0));
-        const double s = c * t;
-        const cd e{gr * rg, -gi * rg};                     // conj(g)/|g|
+        big |= ag2 > kBig * ab;
+        const JacobiRot jr = jacobi_rot(a, bb, gr, gi, ag2);
 #pragma unroll
         for (int tt = 0; tt < R; ++tt) {
           const int rr = lt + tt * TM;
-          const cd ye = cmul(e, y[tt]);
-          sh.mat[ci * LD + rr] = cd{fma(c, x[tt].re, -s * ye.re), fma(c, x[tt].im, -s * ye.im)};
-          sh.mat[cj * LD + rr] = cd{fma(s, x[tt].re, c * ye.re), fma(s, x[tt].im, c * ye.im)};
+          jacobi_apply(jr, x[tt], y[tt]);
+          sh.mat[ci * LD + rr] = x[tt];
+          sh.mat[cj * LD + rr] = y[tt];
         }
       }
-      __syncthreads();
+      wave_sync();
       if (q > 0) ci = (ci == NP - 1) ? 1 : ci + 1;
       cj = (cj == NP - 1) ? 1 : cj + 1;
     }
     // Converged when nothing was rotated, or when every rotated pair of this sweep was already
-    // within 1e-8 of orthogonal: one-sided Jacobi converges quadratically, so the columns are
-    // then orthogonal to ~1e-16 and a verification sweep would rotate nothing.
-    converged = !__syncthreads_or(rotated & big);
+    // close to orthogonal: one-sided Jacobi converges quadratically, so a sweep whose pairs
+    // were all within delta of orthogonal leaves them within ~delta^2.  delta = 1e-8 (columns
+    // orthogonal to ~1e-16) for FP64 storage; 1e-4 (~1e-8, below the 2^-24 rounding of the
+    // stored tensors) for FP32 storage.
+    converged = __ballot(rotated & big) == 0;
   }
-  for (int col = tid; col < N; col += kLayerThreads) {
+  // sig2[c] = |w_c|^2: each team reduces one column at a time
+#pragma unroll
+  for (int c0 = 0; c0 < NP; c0 += P) {
+    const int col = c0 + q;
+    const bool own = active && col < N;
     double s2 = 0.0;
-    for (int rr = 0; rr < MP; ++rr) {
-      const cd v = sh.mat[col * LD + rr];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const cd v = own ? sh.mat[col * LD + lt + t * TM] : cd{0.0, 0.0};
       s2 = fma(v.re, v.re, fma(v.im, v.im, s2));
     }
-    sh.sig2[col] = s2;
+    s2 = team_sum<TM>(s2);
+    if (own && lt == 0) sh.sig2[col] = s2;
   }
-  __syncthreads();
+  wave_sync();
   return converged ? 0 : kImgNoConvergence;
 }
 
 template <int S, typename T>
-__device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
+__device__ __forceinline__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
   const JShape js = jacobi_shape(M, N);
 #define ANOMPS_JT(NPV, RV)                                                           \
   if (js.NP == NPV && js.R == RV) {                                                  \
@@ -272,10 +280,12 @@ __device__ int jacobi_columns(LayerShared<S, T>& sh, int M, int N) {
 //            index r = a*2 + s;
 //  kHhBlock2 (two blocks u = 0, 1 holding the s = u rows of the centre): A[(a,s)][c] =
 //            Q_u[a][c - u*ncb] if s = u, else 0.
-enum : int { kHhCanon = 0, kHhLadder = 1, kHhBlock2 = 2 };
+//  kHhBlockLds (blocks as kHhBlock2): Q kept in LDS instead, ta[r*SP + c] = Q_blk[r][c - blk*ncb]
+//            for the global column c.
+enum : int { kHhCanon = 0, kHhLadder = 1, kHhBlock2 = 2, kHhBlockLds = 3 };
 
 template <int S, typename T, int NC, int R, int MODE>
-__device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
+__device__ __forceinline__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
   constexpr int LD = LayerShared<S, T>::LD;
   constexpr int SP = LayerShared<S, T>::SP;
   constexpr int TM = (kLayerThreads / NC) < 16 ? kLayerThreads / NC : 16;
@@ -316,7 +326,7 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int
         const cd u = d2 > 0.0 ? cd{dr * rd, di * rd} : cd{1.0, 0.0};
         beta = cd{-u.re * alpha, -u.im * alpha};
         v0 = cd{u.re * (ad + alpha), u.im * (ad + alpha)};
-        coef = 1.0 / (alpha * (alpha + ad));                // 2 / |v|^2
+        coef = rcp_full(alpha * (alpha + ad));              // 2 / |v|^2
       }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
@@ -330,7 +340,7 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int
       }
       if (lt == 0) sh.sig2[c] = coef;
     }
-    __syncthreads();
+    wave_sync();
     if (own && lc > j) {
       const int pc = base + j;
       const double coef = sh.sig2[pc];
@@ -383,6 +393,8 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int
         } else if constexpr (MODE == kHhBlock2) {
           store_c<T, double>(slot, (size_t)(rr * 2 + blk) * S + c, x[t]);
           store_c<T, double>(slot, (size_t)(rr * 2 + 1 - blk) * S + c, cd{0.0, 0.0});
+        } else if constexpr (MODE == kHhBlockLds) {
+          sh.ta[rr * SP + c] = x[t];
         } else {
           // row c of Q^H = conj(column c of Q)
           const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
@@ -391,7 +403,7 @@ __device__ void householder_lq(LayerShared<S, T>& sh, int M, int N, int ncb, int
       }
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
 __host__ __device__ inline int lq_rows_per_lane(int M, int N) {
@@ -401,7 +413,7 @@ __host__ __device__ inline int lq_rows_per_lane(int M, int N) {
 }
 
 template <int S, typename T, int MODE>
-__device__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
+__device__ __forceinline__ int lq_columns(LayerShared<S, T>& sh, int M, int N, int ncb, int Dr, T* slot) {
   const int nc = pow2ceil(N < 1 ? 1 : N), r = lq_rows_per_lane(M, N);
 #define ANOMPS_LQ(NCV, RV)                                                                  \
   if (nc == NCV && r == RV) {                                                              \
@@ -452,7 +464,7 @@ __device__ __forceinline__ Gate2 site_gate(int mode, int k, const double* theta,
 
 // Apply a one-qubit gate to the physical index of the (Dl x 2 x Dr) tensor in ta.
 template <int S, typename T>
-__device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, const Gate2& g) {
+__device__ __forceinline__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, const Gate2& g) {
   constexpr int SP = LayerShared<S, T>::SP;
   const FastDiv fd(Dr);
   for (int idx = threadIdx.x; idx < Dl * Dr; idx += kLayerThreads) {
@@ -465,8 +477,38 @@ __device__ void apply_gate(LayerShared<S, T>& sh, int Dl, int Dr, const Gate2& g
     sh.ta[(a * 2 + 0) * SP + b] = w0;
     sh.ta[(a * 2 + 1) * SP + b] = w1;
   }
-  __syncthreads();
+  wave_sync();
 }
+
+// FP64 value of lane `lane` in every lane (two scalar reads).
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd read_lane(cd v, int lane) {
+  return cd{read_lane(v.re, lane), read_lane(v.im, lane)};
+}
+
+// One-qubit gates of a sweep, computed 64 sites at a time: lane l holds the gate of site
+// 64*chunk + l, all lanes evaluate theirs together (one pass of the angle loads and sincos)
+// when the sweep enters a chunk, and a site's gate is then read from its lane as scalars.
+struct LaneGates {
+  Gate2 g{};
+  int chunk = -1;
+  __device__ __forceinline__ Gate2 get(int mode, int k, int n, const double* theta,
+                                       const double* phi, const double* pix) {
+    const int ch = k >> 6;
+    if (ch != chunk) {
+      const int kk = (ch << 6) + (int)threadIdx.x;
+      if (kk < n) g = site_gate(mode, kk, theta, phi, pix);
+      chunk = ch;
+    }
+    const int l = k & 63;
+    return Gate2{read_lane(g.u00, l), read_lane(g.u01, l), read_lane(g.u10, l),
+                 read_lane(g.u11, l)};
+  }
+};
 
 // Register prefetch of one site tensor (Dl x 2 x Dr, storage type) so that its HBM/L2
 // latency overlaps the factorisation of the current bond.
@@ -476,7 +518,7 @@ struct SitePrefetch {
   static constexpr int SP = LayerShared<S, T>::SP;
   cx<T> v[PF];
   int Dl = 0, Dr = 0;
-  __device__ void load(const T* slot, int dl, int dr) {
+  __device__ __forceinline__ void load(const T* slot, int dl, int dr) {
     Dl = dl;
     Dr = dr;
     const FastDiv fd(Dr);
@@ -489,7 +531,7 @@ struct SitePrefetch {
       }
     }
   }
-  __device__ void commit(cx<T>* dst) const {
+  __device__ __forceinline__ void commit(cx<T>* dst) const {
     const FastDiv fd(Dr);
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
@@ -500,7 +542,7 @@ struct SitePrefetch {
 };
 
 template <int S, typename T>
-__device__ void store_tensor(T* slot, const cd* src, int Dl, int Dr) {
+__device__ __forceinline__ void store_tensor(T* slot, const cd* src, int Dl, int Dr) {
   constexpr int SP = LayerShared<S, T>::SP;
   const FastDiv fd(Dr);
   for (int idx = threadIdx.x; idx < Dl * 2 * Dr; idx += kLayerThreads) {
@@ -530,14 +572,15 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
   if (!from_lds) {
     pf.load(st + (size_t)(n - 1) * SLOT, dims(n - 2), 1);
     pf.commit(sh.tb);
-    __syncthreads();
+    wave_sync();
     for (int idx = tid; idx < dims(n - 2) * 2; idx += kLayerThreads) sh.ta[idx * SP] = to_cd(sh.tb[idx * SP]);
-    __syncthreads();
+    wave_sync();
   }
+  LaneGates lg;
   for (int k = n - 1; k >= 1; --k) {
     const int Dl = dims(k - 1), Dr = dims(k), Dll = dims(k - 2);
     pf.load(st + (size_t)(k - 1) * SLOT, Dll, Dl);
-    if (mode != kGateNone) apply_gate<S, T>(sh, Dl, Dr, site_gate(mode, k, theta, phi, pix));
+    if (mode != kGateNone) apply_gate<S, T>(sh, Dl, Dr, lg.get(mode, k, n, theta, phi, pix));
     // mat = t^H: rows (s, b) -> s*Dr + b, columns a.
     const int M = 2 * Dr, N = Dl;
     const FastDiv fm(M);
@@ -546,11 +589,11 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
       const int s_ = rr >= Dr, b = rr - (s_ ? Dr : 0);
       sh.mat[a * LD + rr] = cconj(sh.ta[(a * 2 + s_) * SP + b]);
     }
-    __syncthreads();
+    wave_sync();
     // t = L Q: Q (right-canonical rows) goes to site k, L to uq.
     flags |= lq_columns<S, T, kHhCanon>(sh, M, N, N, Dr, st + (size_t)k * SLOT);
     pf.commit(sh.tb);
-    __syncthreads();
+    wave_sync();
     const FastDiv fdl(Dl);
     for (int idx = tid; idx < Dll * 2 * Dl; idx += kLayerThreads) {
       const int row = fdl.q(idx), a = fdl.r(idx);
@@ -558,9 +601,130 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
       for (int j = 0; j < Dl; ++j) cfma(acc, to_cd(sh.tb[row * SP + j]), sh.uq[j * SP + a]);
       sh.ta[row * SP + a] = acc;
     }
-    __syncthreads();
+    wave_sync();
   }
-  if (mode != kGateNone) apply_gate<S, T>(sh, 1, dims(0), site_gate(mode, 0, theta, phi, pix));
+  if (mode != kGateNone) apply_gate<S, T>(sh, 1, dims(0), lg.get(mode, 0, n, theta, phi, pix));
+  return flags;
+}
+
+// Jacobi SVD split of a CNOT bond whose left bond has grown (Dl > Dc), through the block
+// factorisation of the two-site matrix: Theta'[(a,s),(t,b)] = sum_c C[a,s,c] B[c, t XOR s, b]
+// = blockdiag(C_0, C_1) M with C_u = C[:, u, :] (Dl x Dc, the centre in ta) and
+// M[(u,c),(t,b)] = B[c, t XOR u, b] (the neighbour in tb).  With C_u = Q_u R_u (two Householder
+// blocks, FP64), Theta' = blockdiag(Q_0, Q_1) K, K = blockdiag(R_0, R_1) M (2Dc x 2Dr), and
+// blockdiag(Q) has orthonormal columns, so Theta' and K have the same singular values and right
+// singular vectors, and U_Theta = blockdiag(Q) U_K: the one-sided Jacobi runs on K, which has
+// 2Dc instead of 2Dl rows.  The truncation, renormalisation and discarded weight are those of
+// the SVD of Theta'.  Out: A[k] = blockdiag(Q) U_K in uq as [(a*2 + s)][j] (stored by the
+// caller), the new centre U_K^H K / |sigma_kept| in ta as [j][t][b]; *terr (if not null) gets
+// the discarded weight.  Needs 2Dr <= S (the products X_s below go to mat's columns >= 2Dr).
+template <int S, typename T>
+__device__ __forceinline__ int svd_split_block(LayerShared<S, T>& sh, int Dl, int Dc, int Dr, int D,
+                                               double* terr) {
+  constexpr int LD = LayerShared<S, T>::LD;
+  constexpr int SP = LayerShared<S, T>::SP;
+  const int tid = threadIdx.x;
+  // C_u into mat's columns u*Dc + c (rows a), then C_u = Q_u R_u: Q_u -> ta, conj(R_u) -> uq.
+  {
+    const FastDiv fdl(Dl);
+    for (int idx = tid; idx < 2 * Dc * Dl; idx += kLayerThreads) {
+      const int col = fdl.q(idx), a = fdl.r(idx);
+      const int u = col >= Dc, c = col - (u ? Dc : 0);
+      sh.mat[col * LD + a] = sh.ta[(a * 2 + u) * SP + c];
+    }
+  }
+  wave_sync();
+  int flags = lq_columns<S, T, kHhBlockLds>(sh, Dl, 2 * Dc, Dc, 0, nullptr);
+  // K[(u,c')][(t,b)] = sum_{c >= c'} R_u[c'][c] B[c][t XOR u][b] -> mat (column-major, rows
+  // padded with zeros to the Jacobi tile's height).
+  const int Mk = 2 * Dc, N = 2 * Dr;
+  const int MP = jacobi_shape(Mk, N).MP;
+  {
+    const FastDiv fmp(MP), fdc(Dc);
+    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
+      const int col = fmp.q(idx), row = fmp.r(idx);
+      const int t = col >= Dr, b = col - (t ? Dr : 0);
+      cd acc{0.0, 0.0};
+      if (row < Mk) {
+        const int u = row >= Dc, cp = row - (u ? Dc : 0);
+        for (int c = cp; c < Dc; ++c)
+          cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), to_cd(sh.tb[(c * 2 + (t ^ u)) * SP + b]));
+      }
+      sh.mat[col * LD + row] = acc;
+    }
+  }
+  wave_sync();
+  flags |= jacobi_columns<S, T>(sh, Mk, N);
+  const double tiny2 = sh.tiny2;
+  // rank, column scales, kept and discarded weights (as in the direct split)
+  double vk = 0.0, vd = 0.0;
+  if (tid < N) {
+    double v = sh.sig2[tid];
+    if (!(v >= 0.0)) v = 0.0;
+    int rk = 0;
+    for (int i = 0; i < N; ++i) {
+      double w = sh.sig2[i];
+      if (!(w >= 0.0)) w = 0.0;
+      rk += (w > v) || (w == v && i < tid);
+    }
+    sh.rank[rk] = tid;
+    sh.isig[rk] = v > tiny2 ? rsqrt_full(v) : 0.0;
+    if (rk < D) vk = v; else vd = v;
+  }
+  const double kept = wave_sum(vk), disc = wave_sum(vd);
+  wave_sync();
+  if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
+  const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
+  if (tid == 0 && terr) *terr = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
+  // X_s[j][c] = sum_{c' <= c} conj(U_K[(s,c')][j]) R_s[c'][c] -> xs[(s*D + j)*Dc + c]
+  cd* xs = sh.mat + N * LD;
+  {
+    const FastDiv fdc(Dc), fdd(D);
+    for (int idx = tid; idx < 2 * D * Dc; idx += kLayerThreads) {
+      const int sj = fdc.q(idx), c = fdc.r(idx);
+      const int s_ = sj >= D, j = sj - (s_ ? D : 0);
+      const cd* w = sh.mat + sh.rank[j] * LD + s_ * Dc;
+      cd acc{0.0, 0.0};
+      for (int cp = 0; cp <= c; ++cp) {
+        const cd r = sh.uq[(s_ * Dc + c) * SP + cp];  // conj(R_s[cp][c])
+        const cd u = w[cp];
+        // conj(u) * R = conj(u) * conj(r) = conj(u * r)
+        acc.re = fma(u.re, r.re, fma(-u.im, r.im, acc.re));
+        acc.im = fma(-u.re, r.im, fma(-u.im, r.re, acc.im));
+      }
+      xs[sj * Dc + c] = cscale(acc, sh.isig[j]);
+    }
+  }
+  wave_sync();
+  // A[k][(a,s)][j] = sum_c' Q_s[a][c'] U_K[(s,c')][j] -> uq
+  {
+    const FastDiv fd(D);
+    for (int idx = tid; idx < 2 * Dl * D; idx += kLayerThreads) {
+      const int row = fd.q(idx), j = fd.r(idx);
+      const int a = row >> 1, s_ = row & 1;
+      const cd* w = sh.mat + sh.rank[j] * LD + s_ * Dc;
+      const cd* q = sh.ta + a * SP + s_ * Dc;
+      cd acc{0.0, 0.0};
+      for (int cp = 0; cp < Dc; ++cp) cfma(acc, q[cp], w[cp]);
+      sh.uq[row * SP + j] = cscale(acc, sh.isig[j]);
+    }
+  }
+  wave_sync();
+  // centre[j][(t,b)] = sum_s sum_c X_s[j][c] B[c][t XOR s][b] / |sigma_kept| -> ta
+  {
+    const FastDiv f2r(2 * Dr);
+    for (int idx = tid; idx < D * 2 * Dr; idx += kLayerThreads) {
+      const int j = f2r.q(idx), o = f2r.r(idx);
+      const int t = o >= Dr, b = o - (t ? Dr : 0);
+      cd acc{0.0, 0.0};
+      for (int c = 0; c < Dc; ++c) {
+        cfma(acc, xs[j * Dc + c], to_cd(sh.tb[(c * 2 + t) * SP + b]));
+        cfma(acc, xs[(D + j) * Dc + c], to_cd(sh.tb[(c * 2 + (t ^ 1)) * SP + b]));
+      }
+      sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
+    }
+  }
+  wave_sync();
   return flags;
 }
 
@@ -579,11 +743,20 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
   const int tid = threadIdx.x;
   int flags = 0;
   pf.load(st + (size_t)1 * SLOT, before(0), before(1));
+  // A truncated bond's U stays in uq and is stored at the start of the next bond, after that
+  // bond's wait for its prefetched neighbour: the wait for a load also waits for every store
+  // issued before it, so the store is issued a whole bond before the next such wait.
+  int pend_k = -1, pend_dl = 0, pend_d = 0;
   for (int k = 0; k <= n - 2; ++k) {
     const int Dl = after(k - 1), Dc = before(k), Dr = before(k + 1), D = after(k);
     const int cx = (parity < 0 || (k & 1) == parity) ? 1 : 0;
     pf.commit(sh.tb);
-    __syncthreads();
+    wave_sync();
+    if (pend_k >= 0) {
+      store_tensor<S, T>(st + (size_t)pend_k * SLOT, sh.uq, pend_dl, pend_d);
+      wave_sync();
+      pend_k = -1;
+    }
     if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
     if (exact_qr && ((cx && D == 2 * Dc && Dl >= Dc) || (!cx && D == Dc && 2 * Dl >= Dc))) {
       // The bond keeps every singular value of a factorisation with inner dimension D: split
@@ -601,6 +774,16 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
       }
       continue;
     }
+    // The block route pays only where it shortens the Jacobi tile (fewer rows per lane); for
+    // smaller matrices the direct split is cheaper than the extra factorisation and products.
+    if (cx && Dl > Dc && 2 * Dr <= S &&
+        jacobi_shape(2 * Dc, 2 * Dr).R < jacobi_shape(2 * Dl, 2 * Dr).R) {
+      flags |= svd_split_block<S, T>(sh, Dl, Dc, Dr, D, trunc_err ? trunc_err + k : nullptr);
+      pend_k = k;
+      pend_dl = Dl;
+      pend_d = D;
+      continue;
+    }
     const int M = 2 * Dl, N = 2 * Dr;
     const int MP = jacobi_shape(M, N).MP;
     // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR (cx s), b]   (CNOT control k).
@@ -616,7 +799,7 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
         sh.mat[col * LD + row] = acc;
       }
     }
-    __syncthreads();
+    wave_sync();
     if (exact_qr && D == (M < N ? M : N)) {
       // The bond keeps every singular value: the split needs no SVD (the centre is in canonical
       // position, so the kept weight is |Theta'|_F^2 and the discarded weight is 0).
@@ -630,13 +813,15 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
       if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
       if (cx && tid == 0 && trunc_err) trunc_err[k] = 0.0;
       flags |= exact_split<S, T>(sh, st + (size_t)k * SLOT, M, N, D, Dr, f > 0.0 ? rsqrt_full(f) : 0.0);
-      __syncthreads();
+      wave_sync();
       continue;
     }
     flags |= jacobi_columns<S, T>(sh, M, N);
     const double tiny2 = sh.tiny2;
-    // Rank columns by singular value (descending, ties by index; NaN counts as zero); thread c
-    // owns column c (N <= 2S <= 64).
+    // Rank columns by singular value (descending, ties by index; NaN counts as zero); lane c
+    // owns column c (N <= 2S <= 64), records the scale 1/|w_c| of its U column (0 for a
+    // numerically zero column) under its rank, and the kept and discarded weights are wave sums.
+    double vk = 0.0, vd = 0.0;
     if (tid < N) {
       double v = sh.sig2[tid];
       if (!(v >= 0.0)) v = 0.0;
@@ -647,14 +832,11 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
         rk += (w > v) || (w == v && i < tid);
       }
       sh.rank[rk] = tid;
+      sh.isig[rk] = v > tiny2 ? rsqrt_full(v) : 0.0;
+      if (rk < D) vk = v; else vd = v;
     }
-    __syncthreads();
-    double kept = 0.0, disc = 0.0;
-    for (int r = 0; r < N; ++r) {
-      double v = sh.sig2[sh.rank[r]];
-      if (!(v >= 0.0)) v = 0.0;
-      if (r < D) kept += v; else disc += v;
-    }
+    const double kept = wave_sum(vk), disc = wave_sum(vd);
+    wave_sync();
     if (!isfinite(kept) || !isfinite(disc) || !(kept > 0.0)) flags |= kImgNonfinite;
     const double inv_norm = (kept > 0.0) ? rsqrt_full(kept) : 0.0;
     if (cx && tid == 0 && trunc_err) trunc_err[k] = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
@@ -663,15 +845,13 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
       const FastDiv fd(D);
       for (int idx = tid; idx < M * D; idx += kLayerThreads) {
         const int r = fd.q(idx), j = fd.r(idx);
-        const int c = sh.rank[j];
-        const double s2 = sh.sig2[c];
-        cd v{0.0, 0.0};
-        if (s2 > tiny2) v = cscale(sh.mat[c * LD + r], rsqrt_full(s2));
-        sh.uq[r * SP + j] = v;
+        sh.uq[r * SP + j] = cscale(sh.mat[sh.rank[j] * LD + r], sh.isig[j]);
       }
     }
-    __syncthreads();
-    store_tensor<S, T>(st + (size_t)k * SLOT, sh.uq, Dl, D);
+    wave_sync();
+    pend_k = k;
+    pend_dl = Dl;
+    pend_d = D;
     // X_s = U_s^H A_s  ->  mat[(s*S + j)*SP + c]
     {
       const FastDiv fdc(Dc), fdd(D);
@@ -684,7 +864,7 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
         sh.mat[(s_ * S + j) * SP + c] = acc;
       }
     }
-    __syncthreads();
+    wave_sync();
     // New centre S V^H = U^H Theta' / |sigma_kept|  ->  ta[(j*2+t)*SP + b]
     {
       const FastDiv f2r(2 * Dr);
@@ -699,8 +879,9 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
         sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
+  if (pend_k >= 0) store_tensor<S, T>(st + (size_t)pend_k * SLOT, sh.uq, pend_dl, pend_d);
   store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, after(n - 2), 1);
   return flags;
 }
@@ -778,7 +959,7 @@ __device__ __forceinline__ int block_split(LayerShared<S, T>& sh, T* slot, int D
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   int flags = lq_columns<S, T, kHhBlock2>(sh, Dl, 2 * Dc, Dc, 0, slot);
   const FastDiv f2r(2 * Dr);
   for (int idx = tid; idx < 2 * Dc * 2 * Dr; idx += kLayerThreads) {
@@ -789,7 +970,7 @@ __device__ __forceinline__ int block_split(LayerShared<S, T>& sh, T* slot, int D
     for (int c = cp; c < Dc; ++c) cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), gb[(c * 2 + tt) * SP + b]);
     sh.ta[(j * 2 + t) * SP + b] = cscale(acc, scale);
   }
-  __syncthreads();
+  wave_sync();
   return flags;
 }
 
@@ -809,7 +990,7 @@ __device__ __forceinline__ int plain_split(LayerShared<S, T>& sh, T* slot, int D
       sh.mat[c * LD + row] = sh.ta[row * SP + c];
     }
   }
-  __syncthreads();
+  wave_sync();
   int flags = lq_columns<S, T, kHhLadder>(sh, M, Dc, Dc, 0, slot);
   const FastDiv f2r(2 * Dr);
   for (int idx = tid; idx < Dc * 2 * Dr; idx += kLayerThreads) {
@@ -819,7 +1000,7 @@ __device__ __forceinline__ int plain_split(LayerShared<S, T>& sh, T* slot, int D
     for (int c = j; c < Dc; ++c) cfma(acc, cconj(sh.uq[c * SP + j]), to_cd(sh.tb[(c * 2 + t) * SP + b]));
     sh.ta[(j * 2 + t) * SP + b] = cscale(acc, scale);
   }
-  __syncthreads();
+  wave_sync();
   return flags;
 }
 
@@ -875,18 +1056,18 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
   int flags = 0;
   pf.load(st, 1, before(0));
   pf.commit(sh.tb);
-  __syncthreads();
+  wave_sync();
   pf.load(st + SLOT, before(0), before(1));
   for (int idx = tid; idx < 2 * before(0); idx += kLayerThreads) {
     const int s_ = idx / before(0), c = idx - s_ * before(0);
     sh.ta[s_ * SP + c] = to_cd(sh.tb[s_ * SP + c]);
   }
-  __syncthreads();
+  wave_sync();
   apply_gate<S, T>(sh, 1, before(0), site_gate(kGateRyRz, 0, theta, phi, nullptr));
   for (int k = 0; k <= n - 2; ++k) {
     const int Dl = after(k - 1), Dc = before(k), Dr = before(k + 1), D = after(k);
     pf.commit(sh.tb);
-    __syncthreads();
+    wave_sync();
     if (k + 2 <= n - 1) pf.load(st + (size_t)(k + 2) * SLOT, before(k + 1), before(k + 2));
     if (D == 2 * Dc && Dl >= Dc) {
       flags |= block_split<S, T>(sh, st + (size_t)k * SLOT, Dl, Dc, Dr,
@@ -908,7 +1089,7 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
         sh.uq[(c * 2 + 1) * SP + b] = w1;
       }
     }
-    __syncthreads();
+    wave_sync();
     const int M = 2 * Dl, N = 2 * Dr;
     {
       const FastDiv fm(M), fdr(Dr);
@@ -920,10 +1101,10 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
         sh.mat[col * LD + row] = acc;
       }
     }
-    __syncthreads();
+    wave_sync();
     flags |= exact_split<S, T>(sh, st + (size_t)k * SLOT, M, N, D, Dr, 1.0);
     if (tid == 0 && trunc_err) trunc_err[k] = 0.0;
-    __syncthreads();
+    wave_sync();
   }
   const int Dn = after(n - 2);
   double f = 0.0;
@@ -935,7 +1116,7 @@ __device__ __forceinline__ int qr_sweep(LayerShared<S, T>& sh, T* st, int n, Bef
   if (!isfinite(f) || !(f > 0.0)) flags |= kImgNonfinite;
   const double scale = f > 0.0 ? rsqrt_full(f) : 0.0;
   for (int idx = tid; idx < 2 * Dn; idx += kLayerThreads) sh.ta[idx * SP] = cscale(sh.ta[idx * SP], scale);
-  __syncthreads();
+  wave_sync();
   store_tensor<S, T>(st + (size_t)(n - 1) * SLOT, sh.ta, Dn, 1);
   return flags;
 }
@@ -984,14 +1165,8 @@ __device__ __forceinline__ cd gated_at(const At& at, const Gate2& g, int a, int 
 
 __device__ __forceinline__ bool finite_c(cd v) { return isfinite(v.re) && isfinite(v.im); }
 
-// Orders LDS accesses across the lanes of a one-wavefront workgroup: waits for the wave's own
-// LDS operations and keeps the compiler from moving memory accesses across, but leaves its
-// global loads in flight (a __syncthreads fences global memory too, i.e. waits for every
-// outstanding load and store, which would undo the prefetches below).
-__device__ __forceinline__ void lds_sync() {
-  static_assert(kLayerThreads == 64, "one wavefront per workgroup");
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-}
+// LDS ordering of the one-wavefront workgroups (see wave_sync).
+__device__ __forceinline__ void lds_sync() { wave_sync(); }
 
 // The bit a site passes to its right bond.  Ladder: its output y.  The paper's brickwork layer
 // (§II-B, Eq. (2); CNOTs on the even bonds, then on the odd ones), written the same way with
@@ -1289,8 +1464,11 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
   if (program == kLayerHRyBrickwork) {
     auto dmid = [&](int k) { return bond_dim(n, chi, (k & 1) ? layer : layer + 1, k); };
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateHRy, theta, phi, pix, false, pf);
+    __syncthreads();  // each sweep's global stores are read back by the next sweep
     flags |= cnot_sweep<S, T>(sh, st, n, dold, dmid, 0, trunc_err, pf, exact_qr);
+    __syncthreads();
     flags |= canon_sweep<S, T>(sh, st, n, dmid, kGateNone, theta, phi, pix, true, pf);
+    __syncthreads();
     flags |= cnot_sweep<S, T>(sh, st, n, dmid, dnew, 1, trunc_err, pf, exact_qr);
   } else if (exact_qr && layer_keeps_all(n, chi, layer)) {
     MpoPlan plan;
@@ -1301,6 +1479,7 @@ __device__ __forceinline__ void layer_chain(LayerShared<S, T>& sh, T* st, int n,
       flags |= qr_sweep<S, T>(sh, st, n, dold, dnew, theta, phi, trunc_err, pf);
   } else {
     flags |= canon_sweep<S, T>(sh, st, n, dold, kGateRyRz, theta, phi, pix, false, pf);
+    __syncthreads();  // the sweep's stores of sites 1..n-1 are read back by the ladder
     flags |= cnot_sweep<S, T>(sh, st, n, dold, dnew, -1, trunc_err, pf, exact_qr);
   }
   if (threadIdx.x == 0 && flags) status[0] |= flags;

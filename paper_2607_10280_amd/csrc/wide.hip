@@ -10,6 +10,8 @@
 // canonical sweep, one-sided Jacobi (round-robin, FP64) for the ladder, the same convergence
 // test, ranking, renormalisation and status flags.  The measurement computes in FP64 and
 // stores environments and outputs in the batch's storage type.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -42,28 +44,21 @@ __device__ __forceinline__ double wv_sum(double v) {
   return v;
 }
 
-template <int CTRL>
-__device__ __forceinline__ double w_dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
 // Sum over the 16 lanes of a DPP row (mirror, half-mirror and two quad swaps); every lane of
 // the row ends with the same value.
 __device__ __forceinline__ double team_sum16(double v) {
-  v += w_dpp<0x140>(v);
-  v += w_dpp<0x141>(v);
-  v += w_dpp<0x4E>(v);
-  v += w_dpp<0xB1>(v);
+  v += dpp_mov_d<0x140>(v);
+  v += dpp_mov_d<0x141>(v);
+  v += dpp_mov_d<0x4E>(v);
+  v += dpp_mov_d<0xB1>(v);
   return v;
 }
 
 // Sum over each half (8 lanes) of a DPP row: half-mirror, then the two quad swaps.
 __device__ __forceinline__ double team_sum8(double v) {
-  v += w_dpp<0x141>(v);
-  v += w_dpp<0x4E>(v);
-  v += w_dpp<0xB1>(v);
+  v += dpp_mov_d<0x141>(v);
+  v += dpp_mov_d<0x4E>(v);
+  v += dpp_mov_d<0xB1>(v);
   return v;
 }
 
@@ -208,7 +203,7 @@ __device__ void wide_lq(WideShared& sh, const WideWs& w, int S, int M, int N, in
       const cd u = d2 > 0.0 ? cd{dr * rd, di * rd} : cd{1.0, 0.0};
       beta = cd{-u.re * alpha, -u.im * alpha};
       v0 = cd{u.re * (ad + alpha), u.im * (ad + alpha)};
-      coef = 1.0 / (alpha * (alpha + ad));
+      coef = rcp_full(alpha * (alpha + ad));
     }
     for (int a = tid; a < N; a += kWT)
       w.uq[(size_t)j * S + a] = a < j ? cconj(vj[a]) : (a == j ? cconj(beta) : cd{0.0, 0.0});
@@ -290,10 +285,12 @@ __device__ __forceinline__ int rr_pos(int i, int r, int NP) {
 // round the NP/2 disjoint pairs of the round-robin tournament are spread over the teams of TEAM
 // lanes; a team holds R rows per lane of both columns in registers, reduces |x|^2, |y|^2 and
 // x^H y with DPP, rotates when |x^H y|^2 > (M eps)^2 |x|^2 |y|^2 and writes both columns back.
-// Stops after a sweep whose rotated pairs were all within 1e-8 of orthogonal.  On return
+// Stops after a sweep whose rotated pairs all had |x^H y|^2 <= big_tol |x|^2 |y|^2 (1e-16 for
+// FP64 storage, 1e-8 for FP32 storage: quadratic convergence leaves the columns orthogonal to
+// ~1e-16 and ~1e-8, the latter below the storage rounding).  On return
 // sig2[c] = |w_c|^2 and sh.tiny2 = 1e-30 |A|_F^2 (columns at or below it count as zero).
 template <int R, int TEAM>
-__device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
+__device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N, double big_tol) {
   constexpr int TEAMS = kWT / TEAM;
   const int tid = threadIdx.x, team = tid / TEAM, lt = tid % TEAM;
   double f = 0.0;
@@ -334,20 +331,15 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
         const double ab = a * bb;
         if (a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
           rotated = 1;
-          big |= ag2 > 1e-16 * ab;
-          const double rg = w_rsqrt(ag2);
-          const double zeta = (bb - a) * 0.5 * rg;
-          const double tt = copysign(1.0 / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0))), zeta);
-          const double c = w_rsqrt(fma(tt, tt, 1.0));
-          const double s = c * tt;
-          const cd e{gr * rg, -gi * rg};  // conj(g)/|g|
+          big |= ag2 > big_tol * ab;
+          const JacobiRot jr = jacobi_rot(a, bb, gr, gi, ag2);
 #pragma unroll
           for (int t = 0; t < R; ++t) {
             const int row = lt + t * TEAM;
-            const cd ye = cmul(e, y[t]);
+            jacobi_apply(jr, x[t], y[t]);
             if (row < M) {
-              xc[row] = cd{fma(c, x[t].re, -s * ye.re), fma(c, x[t].im, -s * ye.im)};
-              yc[row] = cd{fma(s, x[t].re, c * ye.re), fma(s, x[t].im, c * ye.im)};
+              xc[row] = x[t];
+              yc[row] = y[t];
             }
           }
         }
@@ -370,16 +362,16 @@ __device__ int wide_jacobi_r(WideShared& sh, cd* mat, int ld, int M, int N) {
 
 // Teams of 8 lanes (32 column pairs at a time) up to 128 rows, of 16 lanes above: the sweep's
 // rounds are short chains of dependent steps, and more pairs in flight per image shorten them.
-__device__ int wide_jacobi(WideShared& sh, cd* mat, int ld, int M, int N) {
+__device__ int wide_jacobi(WideShared& sh, cd* mat, int ld, int M, int N, double big_tol) {
   if (M <= 128) {
     const int rows = (M + 7) / 8;
-    if (rows <= 1) return wide_jacobi_r<1, 8>(sh, mat, ld, M, N);
-    if (rows <= 2) return wide_jacobi_r<2, 8>(sh, mat, ld, M, N);
-    if (rows <= 4) return wide_jacobi_r<4, 8>(sh, mat, ld, M, N);
-    if (rows <= 8) return wide_jacobi_r<8, 8>(sh, mat, ld, M, N);
-    return wide_jacobi_r<16, 8>(sh, mat, ld, M, N);
+    if (rows <= 1) return wide_jacobi_r<1, 8>(sh, mat, ld, M, N, big_tol);
+    if (rows <= 2) return wide_jacobi_r<2, 8>(sh, mat, ld, M, N, big_tol);
+    if (rows <= 4) return wide_jacobi_r<4, 8>(sh, mat, ld, M, N, big_tol);
+    if (rows <= 8) return wide_jacobi_r<8, 8>(sh, mat, ld, M, N, big_tol);
+    return wide_jacobi_r<16, 8>(sh, mat, ld, M, N, big_tol);
   }
-  return wide_jacobi_r<(256 + kTeam - 1) / kTeam, kTeam>(sh, mat, ld, M, N);
+  return wide_jacobi_r<(256 + kTeam - 1) / kTeam, kTeam>(sh, mat, ld, M, N, big_tol);
 }
 
 // Right-to-left sweep: gates (mode != none) and right-canonical sites n-1..1 by Householder LQ;
@@ -478,7 +470,7 @@ __device__ int wide_cnot(WideShared& sh, const WideWs& w, T* st, int S, int n, B
       __syncthreads();
       continue;
     }
-    flags |= wide_jacobi(sh, w.mat, ld, M, N);
+    flags |= wide_jacobi(sh, w.mat, ld, M, N, std::is_same<T, float>::value ? 1e-8 : 1e-16);
     const double tiny2 = sh.tiny2;
     for (int c = tid; c < N; c += kWT) {
       double v = sh.sig2[c];
