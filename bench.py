@@ -77,6 +77,8 @@ def parse():
                          "(the method; default), qr / mpo = the exact shortcuts")
     ap.add_argument("--no-shortcut", action="store_true",
                     help="skip the extra timing of the exact shortcut (mpo) beside the method")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default pair-kernel schedule instead of tuning it first")
     ap.add_argument("--no-trunc-cell", action="store_true",
                     help="skip the extra timing of the truncating cell (chi = 8)")
     ap.add_argument("--workload", default="headline",
@@ -715,6 +717,16 @@ def main():
                 "graph": use_graph, "avg": avg, "out": outs,
                 "status": batch.status.cpu().numpy()}
 
+    # Pair-kernel launch schedule for this batch shape, chosen by measurement (every candidate
+    # gives the same results bit for bit).
+    tuning = None
+    if anomps.slot_dim(n, chi, L) == 16 and not args.no_tune:
+        from paper_2607_10280_amd import autotune
+        choice, tms, timings = autotune.tune_measure(n, chi, L, B, prec)
+        tuning = {"pair_block_images": choice[0], "pair_waves_per_cu": choice[1],
+                  "measure_ms": round(tms, 4),
+                  "default_measure_ms": round(timings[(0, 0)], 4) if (0, 0) in timings else None,
+                  "candidates": len(timings)}
     mode = args.layers_mode
     head = timed(mode, step, not args.no_graph)
     avg = head["avg"]
@@ -821,6 +833,7 @@ def main():
         "roofline": roofline,
         "roofline_layers": roof_layers,
         "roofline_measure": roof_measure,
+        "tuning": tuning,
     }
 
     if mode != "mpo" and not args.no_shortcut:

@@ -266,6 +266,22 @@ int mps_pauli_pair_expect_noalloc(mps_batch* b, const int32_t* pairs, int32_t m,
                                   hipStream_t stream);
 
 /*
+ * Schedule of the measurement's pair kernel for 16-wide slots (host-side settings of the calling
+ * process, read at each launch):
+ *  pair_block_images : launch order -- the batch is taken in blocks of this many images (rounded
+ *                      up to a multiple of 8), every start site of a block's images before the
+ *                      next block, start site major inside a block; 0 (the default) = the whole
+ *                      batch as one block.
+ *  pair_waves_per_cu : at most this many resident workgroups (one wavefront each) per compute
+ *                      unit, enforced through the launch's LDS allocation; 0 (the default) = as
+ *                      many as the registers allow; otherwise >= 4.
+ * Results do not depend on either: each (image, start site) runs the same arithmetic.  The
+ * autotuner of the Python package chooses them by measurement.  MPS_ERR_INVALID_ARG for values
+ * out of range.
+ */
+int mps_set_measure_tuning(int32_t pair_block_images, int32_t pair_waves_per_cu);
+
+/*
  * Pauli-basis coefficients of the adaptive observables (§II-A, Eq. (4)):
  *   H_q[j][j] = D[q][j]; for the upper positions (0,1),(0,2),(0,3),(1,2),(1,3),(2,3), in this
  *   order, H_q[j][k] = A[q][idx] + i B[q][idx] and H_q[k][j] = conj; basis |s_i s_j>.

@@ -111,6 +111,7 @@ EXPORTS = {
     "mps_pauli_pair_expect_mixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(MixedPlan),
                                                    ctypes.c_void_p]),
     "mps_set_mixed_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "mps_set_measure_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "mps_set_exact_layers": (ctypes.c_int, [ctypes.c_int32]),
     "mps_ano_train_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 4),
     "mps_ano_train_step": (ctypes.c_int, [ctypes.c_void_p] * 9 + [ctypes.c_int32] * 4 +
@@ -413,6 +414,12 @@ def set_exact_layers(mode: int) -> None:
     site as the parity product operator with exact reduction at the chain ends; EXACT_QR splits
     them by QR in one sweep; EXACT_SVD runs the canonical sweep + Jacobi SVD for every layer."""
     _check(lib().mps_set_exact_layers(mode))
+
+
+def set_measure_tuning(pair_block_images: int = 0, pair_waves_per_cu: int = 0) -> None:
+    """Schedule of the 16-wide pair launch: image blocking (0 = the whole batch as one block) and
+    a cap on resident workgroups per compute unit (0 = none)."""
+    _check(lib().mps_set_measure_tuning(pair_block_images, pair_waves_per_cu))
 
 
 def set_mixed_tuning(bucket: int, blocks_per_cu: int) -> None:

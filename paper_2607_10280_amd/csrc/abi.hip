@@ -74,6 +74,11 @@ int check_batch(const mps_batch* b) {
 // ---- mixed request tables
 int g_mixed_blocks_per_cu[MPS_MIXED_BUCKETS] = {0};
 
+// Image blocking of the 16-wide pair launch, in groups of 8 images (0 = the whole batch), and
+// its cap on resident workgroups per compute unit (0 = none).
+int g_pair_block_groups = 0;
+int g_pair_waves_per_cu = 0;
+
 int bucket_of(int S, int prec) {
   int lg = 0;
   while ((2 << lg) < S) ++lg;  // S = 2, 4, 8, 16 -> 0..3
@@ -175,7 +180,7 @@ int measure(mps_batch* b, void* env, const int32_t* pairs, int32_t m, void* out,
                                      b->n_sites, b->chi, S, L, b->batch, (float*)out, stream);
   } else if (S == 16) {
     e = launch_measure16(b->state, env, pairs, m, b->n_sites, b->chi, L, b->batch, out,
-                         b->precision, stream);
+                         b->precision, g_pair_block_groups, g_pair_waves_per_cu, stream);
   } else if (b->precision == MPS_PREC_FP64) {
     e = launch_envs<double, double>((const double*)b->state, (double*)env, b->n_sites, b->chi, S, L, b->batch, stream);
     if (e == hipSuccess)
@@ -485,6 +490,15 @@ int mps_set_exact_layers(int32_t mode) {
     case MPS_EXACT_SVD: set_exact_qr(kExactSvd); break;
     default: return fail(MPS_ERR_INVALID_ARG, "mode=%d", mode);
   }
+  return ok();
+}
+
+int mps_set_measure_tuning(int32_t pair_block_images, int32_t pair_waves_per_cu) {
+  if (pair_block_images < 0 || pair_waves_per_cu < 0 || (pair_waves_per_cu > 0 && pair_waves_per_cu < 4))
+    return fail(MPS_ERR_INVALID_ARG, "pair_block_images=%d pair_waves_per_cu=%d", pair_block_images,
+                pair_waves_per_cu);
+  g_pair_block_groups = (pair_block_images + 7) / 8;
+  g_pair_waves_per_cu = pair_waves_per_cu;
   return ok();
 }
 

@@ -45,7 +45,8 @@ hipError_t launch_pairs(const T* state, const C* env, const int* pairs, int m, i
 // FP64 products (state, environments and outputs FP64), FP32 products, or split-BF16 products
 // with FP32 accumulation.
 hipError_t launch_measure16(const void* state, void* env, const int* pairs, int m, int n, int chi,
-                            int layers, int batch, void* out, int precision, hipStream_t stream);
+                            int layers, int batch, void* out, int precision, int block_groups,
+                            int waves_per_cu, hipStream_t stream);
 
 // Wide slots (S = 32, 64, 128; wide.hip): the same layer and measurement with one 256-lane
 // workgroup per image and the per-bond matrices in an FP64 workspace of

@@ -609,14 +609,21 @@ template <int MODE>
 __device__ __forceinline__ void pairs16_block(const typename MmaReal<MODE>::type* state,
                                               const typename MmaReal<MODE>::type* env,
                                               const int* pairs, int m, int n, int chi, int layers,
-                                              int batch, typename MmaReal<MODE>::type* out) {
+                                              int batch, typename MmaReal<MODE>::type* out,
+                                              int block_groups) {
   constexpr size_t SLOT = (size_t)2 * 16 * 16 * 2;
   constexpr size_t ETILE = (size_t)16 * 16 * 2;
-  // Start site major: every image's start site 0 first, the last sites (for neighbour pairs,
-  // those with only short partners and no carry) last, so that the launch ends on short
-  // workgroups.  Image b still runs on XCD b % NXCD.
+  // Launch order: the images are taken in blocks of `block_groups` groups of NXCD images, and
+  // inside a block start site major (every image's start site 0 first, the last sites -- for
+  // neighbour pairs those with only short partners and no carry -- last).  A block small
+  // enough for its images' tiles to stay in the XCDs' L2 caches reads each tile from HBM once;
+  // the last block still ends the launch on short workgroups.  block_groups >= the number of
+  // groups is one block: start site major over the whole batch.  Image b runs on XCD b % NXCD.
   const int w = blockIdx.x, xcd = w % NXCD, jw = w / NXCD, groups = (batch + NXCD - 1) / NXCD;
-  const int b = NXCD * (jw % groups) + xcd, i = jw / groups;
+  const int bg = (block_groups > 0 && block_groups < groups) ? block_groups : groups;
+  const int per = bg * (n - 1), blk = jw / per, r = jw - blk * per;
+  const int g0 = blk * bg, gc = (groups - g0) < bg ? (groups - g0) : bg;
+  const int b = NXCD * (g0 + r % gc) + xcd, i = r / gc;
   if (b >= batch) return;
   pairs16_image<MODE>(state + (size_t)b * n * SLOT, env + (size_t)b * 2 * (n + 1) * ETILE, pairs,
                       m, n, chi, layers, i, out + (size_t)b * m * 15);
@@ -627,15 +634,16 @@ __device__ __forceinline__ void pairs16_block(const typename MmaReal<MODE>::type
 template <int MODE>
 __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pairs16(
     const float* state, const float* env, const int* pairs, int m, int n, int chi, int layers,
-    int batch, float* out) {
-  pairs16_block<MODE>(state, env, pairs, m, n, chi, layers, batch, out);
+    int batch, float* out, int block_groups) {
+  pairs16_block<MODE>(state, env, pairs, m, n, chi, layers, batch, out, block_groups);
 }
 
 // FP64: every operand and accumulator takes twice the registers.
 __global__ __launch_bounds__(W) void k_pairs16_f64(const double* state, const double* env,
                                                    const int* pairs, int m, int n, int chi,
-                                                   int layers, int batch, double* out) {
-  pairs16_block<kMmaF64>(state, env, pairs, m, n, chi, layers, batch, out);
+                                                   int layers, int batch, double* out,
+                                                   int block_groups) {
+  pairs16_block<kMmaF64>(state, env, pairs, m, n, chi, layers, batch, out, block_groups);
 }
 
 // Mixed request tables (one bucket: S = 16, FP32 or FP64), with the same XCD grouping by request.
@@ -687,8 +695,21 @@ hipError_t launch_measure16_mixed(const mps_request* reqs, int begin, int count,
   return hipGetLastError();
 }
 
+// Dynamic LDS that caps the pair kernel at `waves_per_cu` resident workgroups per compute unit
+// (160 KiB of LDS per CU on gfx950; 0 = no cap): an occupancy setting that leaves the
+// arithmetic of every workgroup unchanged.
+template <typename K>
+size_t pair_lds_cap(K kernel, int waves_per_cu) {
+  if (waves_per_cu <= 0) return 0;
+  hipFuncAttributes attr{};
+  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+  const size_t per = ((size_t)160 * 1024 / (size_t)waves_per_cu) / 512 * 512;
+  return per > attr.sharedSizeBytes ? per - attr.sharedSizeBytes : 0;
+}
+
 hipError_t launch_measure16(const void* state, void* env, const int* pairs, int m, int n, int chi,
-                            int layers, int batch, void* out, int precision, hipStream_t stream) {
+                            int layers, int batch, void* out, int precision, int block_groups,
+                            int waves_per_cu, hipStream_t stream) {
   const int groups = (batch + NXCD - 1) / NXCD;
   const dim3 genv((unsigned)(NXCD * groups * 2)), gpair((unsigned)((size_t)NXCD * groups * (n - 1)));
   hipError_t e;
@@ -696,20 +717,23 @@ hipError_t launch_measure16(const void* state, void* env, const int* pairs, int 
     hipLaunchKernelGGL((k_env16<kMmaF64>), genv, dim3(W), 0, stream, (const double*)state,
                        (double*)env, n, chi, layers, batch);
     if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
-    hipLaunchKernelGGL(k_pairs16_f64, gpair, dim3(W), 0, stream, (const double*)state,
-                       (const double*)env, pairs, m, n, chi, layers, batch, (double*)out);
+    hipLaunchKernelGGL(k_pairs16_f64, gpair, dim3(W), pair_lds_cap(k_pairs16_f64, waves_per_cu),
+                       stream, (const double*)state,
+                       (const double*)env, pairs, m, n, chi, layers, batch, (double*)out, block_groups);
   } else if (precision == MPS_PREC_SPLIT_BF16) {
     hipLaunchKernelGGL((k_env16<kMmaSplitBf16>), genv, dim3(W), 0, stream, (const float*)state,
                        (float*)env, n, chi, layers, batch);
     if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
-    hipLaunchKernelGGL((k_pairs16<kMmaSplitBf16>), gpair, dim3(W), 0, stream, (const float*)state,
-                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out);
+    hipLaunchKernelGGL((k_pairs16<kMmaSplitBf16>), gpair, dim3(W),
+                       pair_lds_cap(k_pairs16<kMmaSplitBf16>, waves_per_cu), stream, (const float*)state,
+                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out, block_groups);
   } else {
     hipLaunchKernelGGL((k_env16<kMmaGauss>), genv, dim3(W), 0, stream, (const float*)state,
                        (float*)env, n, chi, layers, batch);
     if ((e = hipGetLastError()) != hipSuccess || m == 0) return e;
-    hipLaunchKernelGGL((k_pairs16<kMmaGauss>), gpair, dim3(W), 0, stream, (const float*)state,
-                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out);
+    hipLaunchKernelGGL((k_pairs16<kMmaGauss>), gpair, dim3(W),
+                       pair_lds_cap(k_pairs16<kMmaGauss>, waves_per_cu), stream, (const float*)state,
+                       (const float*)env, pairs, m, n, chi, layers, batch, (float*)out, block_groups);
   }
   return hipGetLastError();
 }
