@@ -257,7 +257,8 @@ def run_mixed(args):
         "steps": args.steps, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else "f64", "data": "synthetic",
         "config": {"workload": f"{N} mixed requests, Gaussian blobs, p~U{{6,8,10,12}}, "
-                               f"L~U{{1,2}}, chi=16, H+V pairs", "requests": N},
+                               f"L~U{{1,2}}, chi=16, H+V pairs", "requests": N,
+                   "layers_mode": args.layers_mode},
         "graph": {"images_per_s": round(N / (ms_graph * 1e-3), 1), "ms_per_step": round(ms_graph, 4),
                   "identical_to_eager": bool(graph_same)},
         "plain": {"images_per_s": round(1.0 / plain_s, 1), "requests_timed": int(len(sample))},
@@ -301,6 +302,7 @@ def run_serve(args):
     sat_n = min(N, 4000)
     sat = srv.run(make(np.zeros(sat_n), range(sat_n))).summary()
     qps_sat = sat["throughput_req_per_s"]
+    print(f"[serve] saturation {qps_sat} req/s", file=sys.stderr, flush=True)
     runs = {}
     for frac in (0.5, 0.9):
         arr = inputs.poisson_arrivals(N, frac * qps_sat, 6)
@@ -309,6 +311,8 @@ def run_serve(args):
         lat = np.array(st.latencies_ms)
         order = np.argsort([r.arrival for r in reqs])
         lat_after = np.array([(reqs[i].done_time - reqs[i].arrival) * 1e3 for i in order[warm:]])
+        print(f"[serve] {frac}x done: p99 {np.percentile(lat_after, 99):.1f} ms", file=sys.stderr,
+              flush=True)
         runs[f"{frac}x"] = {"qps": round(frac * qps_sat, 1), "requests": N, "warmup": warm,
                             "latency_ms_p50": round(float(np.percentile(lat_after, 50)), 3),
                             "latency_ms_p99": round(float(np.percentile(lat_after, 99)), 3),
@@ -333,7 +337,7 @@ def run_serve(args):
         "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else "f64", "data": "synthetic",
         "config": {"workload": "single-image requests, p~U{7..16}, L~U{1..4}, "
                                "chi~U{2,4,8,16,32}, readout 84->784 for p=7",
-                   "requests": N, "arena_bytes": arena},
+                   "requests": N, "arena_bytes": arena, "layers_mode": args.layers_mode},
         "saturation": sat, "runs": runs,
         "plain_fifo_0.5x": {**pst.summary(), "requests": plain_n},
         "batch_invariance": {"checked": len(check), "identical": same},
@@ -387,6 +391,7 @@ def run_grid(args):
             else:
                 ref = ofeat.truncated_features(x[sample], th, ph, pairs, chi)[0]
                 kind = "truncated"
+            print(f"[grid] L={L} chi={chi} {ms:.3f} ms", file=sys.stderr, flush=True)
             cells.append({"L": L, "chi": chi, "images_per_s": round(B / (ms * 1e-3), 1),
                           "ms": round(ms, 4), "max_abs_err": float(np.abs(o[sample] - ref).max()),
                           "oracle": kind, "status_nonzero": int(np.count_nonzero(b.status.cpu()))})
@@ -398,7 +403,7 @@ def run_grid(args):
         "steps": args.steps, "higher_is_better": True, "data": "synthetic",
         "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision,
         "config": {"workload": f"{p}x{p} Gaussian blobs, L in 1..4 x chi in {{2,4,8,16}}",
-                   "global_batch": B}, "cells": cells}))
+                   "global_batch": B, "layers_mode": args.layers_mode}, "cells": cells}))
 
 
 def run_paper(args):
@@ -442,7 +447,8 @@ def run_paper(args):
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision, "data": "synthetic",
         "config": {"workload": f"{p}x{p} Gaussian blobs, H + R_Y(2 pi x - pi) + brickwork CNOTs, "
-                               f"L={L}, chi={chi}, {len(pairs)} pairs", "global_batch": B},
+                               f"L={L}, chi={chi}, {len(pairs)} pairs", "global_batch": B,
+                   "layers_mode": args.layers_mode},
         "max_abs_err": float(np.abs(o[sample] - ref).max()),
         "status_nonzero": int(np.count_nonzero(b.status.cpu()))}))
 
@@ -509,7 +515,8 @@ def run_chisweep(args):
         "steps": 1, "higher_is_better": True, "data": "synthetic",
         "dtype": "c64+f64svd" if prec == anomps.PREC_FP32 else args.precision,
         "config": {"workload": f"{p}x{p} Gaussian blobs, R_Y R_Z + CNOT ladder, L={L}, "
-                               f"{len(pairs)} H+V pairs", "global_batch": B},
+                               f"{len(pairs)} H+V pairs", "global_batch": B,
+                   "layers_mode": args.layers_mode},
         "reference_vs_oracle_max_abs_err": float(np.abs(ref[:1] - oracle_ref).max()),
         "cells": cells}))
 
@@ -580,7 +587,7 @@ def run_precision(args):
         "dtype": "c64+f64svd / split_bf16",
         "config": {"workload": f"{p}x{p} Gaussian blobs, L in {{1,2}} x chi in {{16,32,64}} "
                                f"(+ L=4, chi=16), {len(pairs)} H+V pairs", "global_batch": B,
-                   "sampled_images": len(sample)},
+                   "sampled_images": len(sample), "layers_mode": args.layers_mode},
         "cells": cells}))
 
 
@@ -590,6 +597,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.workload != "headline":
+        import torch  # the HIP runtime comes up through torch before the library is loaded
+        torch.cuda.init()
+        from paper_2607_10280_amd import anomps
+        anomps.set_exact_layers(LAYER_MODES[args.layers_mode])
     if args.workload == "mixed":
         return run_mixed(args)
     if args.workload == "serve":
