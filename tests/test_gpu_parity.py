@@ -293,14 +293,20 @@ def test_readout_blocks(A, f64, B, m, out_dim):
 
 
 # ------------------------------------------------------------------ full-size workload
-def test_headline_size_sampled(A):
-    """7x7, L=4, chi=16, batch 1024 (complex64 / FP64 SVD): sampled images against the exact
-    oracle, invariants on every output."""
+@pytest.mark.parametrize("mode", ["svd", "mpo"])
+def test_headline_size_sampled(A, mode):
+    """7x7, L=4, chi=16, batch 1024 (complex64 / FP64 SVD), in the benchmark's layer mode (the
+    canonical sweep + Jacobi SVD ladder) and with the exact shortcut: sampled images against
+    the exact oracle, invariants on every output."""
     p, n, B, L = 7, 49, 1024, 4
     x = inputs.blob_images(B, p, 2)
     th, ph = inputs.layer_angles(L, n, 3 + L)
     pairs = inputs.neighbour_pairs(p)
-    out, st = run(A, x, th, ph, pairs, 16, A.PREC_FP32)
+    try:
+        A.set_exact_layers(A.EXACT_SVD if mode == "svd" else A.EXACT_MPO)
+        out, st = run(A, x, th, ph, pairs, 16, A.PREC_FP32)
+    finally:
+        A.set_exact_layers(A.EXACT_MPO)
     assert np.all(st == 0)
     assert np.all(np.isfinite(out)) and np.abs(out).max() <= 1 + 1e-5
     assert np.all(np.sum(out.astype(np.float64) ** 2, axis=2) <= 3 + 1e-4)
