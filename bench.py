@@ -33,16 +33,18 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # bf16 matrix cores (dense)
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0,
-# the factors a 1 GiB device copy reads), valid only for the kernel source they were taken on.
+# the factors a 1 GiB device copy reads in the same runs), valid only for the kernel source they
+# were taken on (and, for the measurement, the default pair-kernel schedule).
 MEASURED_TRAFFIC = {
-    # one mps_apply_layers call (all four layers): k_mpo_run_core + k_mpo_run_ends
-    "layers": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-               "sha1": "0907698710102818f3f2e5ee101d2b7c003502cf",
-               "bytes": ((2 * 5316.7 + 167936.0) + (2 * 4974.2 + 6260.0)) * 1024},
-    # one measurement call: k_env16 + k_pairs16 (complex64, slot 16)
+    # one k_layer launch (one layer of the canonical sweep + Jacobi SVD ladder), averaged over
+    # the four layers of the headline
+    "layers_svd": {"source": "paper_2607_10280_amd/csrc/layer.hip",
+                   "sha1": "2d8430dff89b080a84dbdf49ae4a3f5de3b1752e",
+                   "bytes": (2 * 37060.0 + 73840.0) * 1024},
+    # one measurement call: k_env16 + k_pairs16 (complex64, slot 16, blocks of 64 images)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
-                "sha1": "c6c9cc4b97a5bb9efc391a340bbd09b0ba75f440",
-                "bytes": (2 * (194730.2 + 439745.1) + (204825.4 + 8715.8)) * 1024},
+                "sha1": "b5a5217119d97090ec7d1394cafbc6362dcc893d",
+                "bytes": (2 * (194600.0 + 222000.0) + (204800.0 + 5570.0)) * 1024},
 }
 
 
@@ -77,8 +79,9 @@ def parse():
                          "(the method; default), qr / mpo = the exact shortcuts")
     ap.add_argument("--no-shortcut", action="store_true",
                     help="skip the extra timing of the exact shortcut (mpo) beside the method")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="keep the default pair-kernel schedule instead of tuning it first")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the pair-kernel schedule by measurement before timing (the "
+                         "library default is blocks of 64 images, no occupancy cap)")
     ap.add_argument("--no-trunc-cell", action="store_true",
                     help="skip the extra timing of the truncating cell (chi = 8)")
     ap.add_argument("--workload", default="headline",
@@ -91,6 +94,9 @@ def parse():
                          "against split-BF16 errors per (L, chi) at 16x16")
     ap.add_argument("--requests", type=int, default=0, help="mixed/serve: number of requests")
     ap.add_argument("--tune-cache", default="", help="mixed/serve: autotuner JSON cache path")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="headline: run only the copy calibration and --steps eager steps, then "
+                         "exit (for counter runs); prints no result line")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of known "
                          "traffic, to scale hardware byte counters)")
@@ -669,6 +675,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.counters_only:
+        # a short program for rocprofv3 counter passes: the copy above, then K eager steps of
+        # the headline batch, nothing else on the GPU
+        anomps.set_exact_layers(LAYER_MODES[args.layers_mode])
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        print(f"[counters] {args.steps} steps of {args.layers_mode} layers done", flush=True)
+        return
+
     def per_call(stepf, count):
         """Average duration of each call of the step (HIP events on the launch stream)."""
         per = {}
@@ -731,14 +747,12 @@ def main():
 
     # Pair-kernel launch schedule for this batch shape, chosen by measurement (every candidate
     # gives the same results bit for bit).
-    tuning = None
-    if anomps.slot_dim(n, chi, L) == 16 and not args.no_tune:
+    tuning = {"pair_block_images": 64, "pair_waves_per_cu": 0, "source": "library default"}
+    if anomps.slot_dim(n, chi, L) == 16 and args.tune:
         from paper_2607_10280_amd import autotune
         choice, tms, timings = autotune.tune_measure(n, chi, L, B, prec)
         tuning = {"pair_block_images": choice[0], "pair_waves_per_cu": choice[1],
-                  "measure_ms": round(tms, 4),
-                  "default_measure_ms": round(timings[(0, 0)], 4) if (0, 0) in timings else None,
-                  "candidates": len(timings)}
+                  "source": "autotune", "measure_ms": round(tms, 4), "candidates": len(timings)}
     mode = args.layers_mode
     head = timed(mode, step, not args.no_graph)
     avg = head["avg"]
@@ -791,6 +805,8 @@ def main():
         meas_peak = PEAK_FP64_TFLOPS if prec == anomps.PREC_FP64 else PEAK_FP32_VALU_TFLOPS
     ach_m = meas_flops / (per_step["measure"] * 1e-3) / 1e12
     traffic_m = _measured_traffic("measure")
+    if (tuning["pair_block_images"], tuning["pair_waves_per_cu"]) != anomps.DEFAULT_MEASURE_SCHEDULE:
+        traffic_m = None  # the counters were taken with the default schedule
     roof_measure = {"bound": meas_bound, "achieved": round(ach_m, 3), "peak": meas_peak,
                     "unit": "TFLOP/s", "frac": round(ach_m / meas_peak, 4),
                     "traffic": None if traffic_m is None else round(traffic_m),
@@ -808,7 +824,7 @@ def main():
         roof_layers = layer_roofline(n, chi, L, B, per_step["layers"], mode)
         traffic_l = _measured_traffic("layers_" + mode)
         if traffic_l is not None:
-            roof_layers["traffic"] = round(traffic_l / L)
+            roof_layers["traffic"] = round(traffic_l)
     dom = "layers" if per_step["layers"] >= per_step["measure"] else "measure"
     roofline = roof_layers if dom == "layers" else roof_measure
 

@@ -270,8 +270,8 @@ int mps_pauli_pair_expect_noalloc(mps_batch* b, const int32_t* pairs, int32_t m,
  * process, read at each launch):
  *  pair_block_images : launch order -- the batch is taken in blocks of this many images (rounded
  *                      up to a multiple of 8), every start site of a block's images before the
- *                      next block, start site major inside a block; 0 (the default) = the whole
- *                      batch as one block.
+ *                      next block, start site major inside a block; 0 = the whole batch as one
+ *                      block.  Default 64.
  *  pair_waves_per_cu : at most this many resident workgroups (one wavefront each) per compute
  *                      unit, enforced through the launch's LDS allocation; 0 (the default) = as
  *                      many as the registers allow; otherwise >= 4.

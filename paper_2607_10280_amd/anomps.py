@@ -416,7 +416,12 @@ def set_exact_layers(mode: int) -> None:
     _check(lib().mps_set_exact_layers(mode))
 
 
-def set_measure_tuning(pair_block_images: int = 0, pair_waves_per_cu: int = 0) -> None:
+# the library's pair-kernel schedule until set_measure_tuning changes it
+DEFAULT_MEASURE_SCHEDULE = (64, 0)
+
+
+def set_measure_tuning(pair_block_images: int = DEFAULT_MEASURE_SCHEDULE[0],
+                       pair_waves_per_cu: int = DEFAULT_MEASURE_SCHEDULE[1]) -> None:
     """Schedule of the 16-wide pair launch: image blocking (0 = the whole batch as one block) and
     a cap on resident workgroups per compute unit (0 = none)."""
     _check(lib().mps_set_measure_tuning(pair_block_images, pair_waves_per_cu))

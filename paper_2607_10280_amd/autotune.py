@@ -20,7 +20,8 @@ import os
 from . import anomps, mixed
 
 DEFAULT_CANDIDATES = (1, 2, 4, 8, 0)  # 0 = as many as fit (the library default)
-# pair-kernel schedules: (images per block, resident workgroups per CU); (0, 0) = the default
+# pair-kernel schedules: (images per block, resident workgroups per CU); the library default is
+# (64, 0), (0, 0) one block of the whole batch with no cap
 MEASURE_CANDIDATES = tuple((blk, w) for blk in (0, 32, 64, 128, 256) for w in (0, 8, 12, 16))
 
 

@@ -75,8 +75,10 @@ int check_batch(const mps_batch* b) {
 int g_mixed_blocks_per_cu[MPS_MIXED_BUCKETS] = {0};
 
 // Image blocking of the 16-wide pair launch, in groups of 8 images (0 = the whole batch), and
-// its cap on resident workgroups per compute unit (0 = none).
-int g_pair_block_groups = 0;
+// its cap on resident workgroups per compute unit (0 = none).  Default: blocks of 64 images,
+// which read each image's tiles from HBM about once (counters: half the traffic of one block)
+// at the same speed.
+int g_pair_block_groups = 8;
 int g_pair_waves_per_cu = 0;
 
 int bucket_of(int S, int prec) {

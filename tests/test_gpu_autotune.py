@@ -43,7 +43,7 @@ def test_pair_schedules_bit_identical(A, B, prec):
                 ref = got
             assert np.array_equal(got, ref), cand
     finally:
-        anomps.set_measure_tuning(0, 0)
+        anomps.set_measure_tuning(*anomps.DEFAULT_MEASURE_SCHEDULE)
     with pytest.raises(anomps.MpsError):
         anomps.set_measure_tuning(-8, 0)
     with pytest.raises(anomps.MpsError):
@@ -65,7 +65,7 @@ def test_tune_measure_and_cache(A, tmp_path):
         assert autotune.load_and_apply(path) == {3: 2}
         assert autotune.load_measure("measure/none", path) is None
     finally:
-        anomps.set_measure_tuning(0, 0)
+        anomps.set_measure_tuning(*anomps.DEFAULT_MEASURE_SCHEDULE)
         anomps.set_mixed_tuning(3, 0)
 
 
