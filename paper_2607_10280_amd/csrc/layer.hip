@@ -128,6 +128,74 @@ struct FastDiv {
   __device__ __forceinline__ int r(int x) const { return p2 ? (x & (d - 1)) : x % d; }
 };
 
+// Small complex products staged in LDS, on the FP64 matrix cores: out(b, i, j) = sum_{k < K}
+// a(b, i, k) bm(b, k, j) for NB independent products of M x N outputs.  The wavefront takes
+// one 16 x 16 output tile at a time and accumulates it over 4-deep slices of k with
+// v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16]
+// and holds D[l / 16 + 4r][l % 16], r < 4); the complex product is four real ones, the real
+// and imaginary parts in two accumulators.  Entries outside M, N or K enter as zeros; the
+// accessors are only called with indices inside their ranges.  At the bond sizes of a chain
+// (M, N, K <= 32) the products are bound by the latency of their operand reads and of the
+// multiply-add chains, which the matrix cores take in a few dozen instructions.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void mfma_cgemm(int NB, int M, int N, int K, FA a, FB bm, FO out) {
+  const int l = threadIdx.x, lr = l & 15, lq = l >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  for (int b = 0; b < NB; ++b)
+    for (int ti = 0; ti < tm; ++ti)
+      for (int tj = 0; tj < tn; ++tj) {
+        const int i = ti * 16 + lr, j = tj * 16 + lr;
+        const bool iok = i < M, jok = j < N;
+        const int ic = iok ? i : M - 1, jc = jok ? j : N - 1;
+        dbl4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (int k0 = 0; k0 < K; k0 += 4) {
+          const int k = k0 + lq;
+          const bool kok = k < K;
+          const int kc = kok ? k : K - 1;
+          cd av = a(b, ic, kc), bv = bm(b, kc, jc);
+          if (!(iok && kok)) av = cd{0.0, 0.0};
+          if (!kok) bv = cd{0.0, 0.0};
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.re, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.im, ci, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.im, bv.im, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.im, bv.re, ci, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = ti * 16 + lq + 4 * r;
+          if (ii < M && jok) out(b, ii, j, cd{cr[r], ci[r]});
+        }
+      }
+}
+
+// The same products on the vector units, one output per lane and step: cheaper than a padded
+// matrix-core tile for fewer than 128 outputs per product (measured at the bond sizes of a
+// 16-wide slot).
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void valu_cgemm(int NB, int M, int N, int K, FA a, FB bm, FO out) {
+  const int mn = M * N;
+  const FastDiv fmn(mn), fn(N);
+  for (int idx = threadIdx.x; idx < NB * mn; idx += kLayerThreads) {
+    const int b = fmn.q(idx), rem = fmn.r(idx);
+    const int i = fn.q(rem), j = fn.r(rem);
+    cd acc{0.0, 0.0};
+    for (int k = 0; k < K; ++k) cfma(acc, a(b, i, k), bm(b, k, j));
+    out(b, i, j, acc);
+  }
+}
+
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void cgemm(int NB, int M, int N, int K, FA a, FB bm, FO out) {
+  if (NB <= 0 || M <= 0 || N <= 0) return;
+  if (M * N >= 128)
+    mfma_cgemm(NB, M, N, K, a, bm, out);
+  else
+    valu_cgemm(NB, M, N, K, a, bm, out);
+}
+
 __host__ __device__ inline int pow2ceil(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -594,13 +662,11 @@ __device__ __forceinline__ int canon_sweep(LayerShared<S, T>& sh, T* st, int n, 
     flags |= lq_columns<S, T, kHhCanon>(sh, M, N, N, Dr, st + (size_t)k * SLOT);
     pf.commit(sh.tb);
     wave_sync();
-    const FastDiv fdl(Dl);
-    for (int idx = tid; idx < Dll * 2 * Dl; idx += kLayerThreads) {
-      const int row = fdl.q(idx), a = fdl.r(idx);
-      cd acc{0.0, 0.0};
-      for (int j = 0; j < Dl; ++j) cfma(acc, to_cd(sh.tb[row * SP + j]), sh.uq[j * SP + a]);
-      sh.ta[row * SP + a] = acc;
-    }
+    // left neighbour times L: ta[row][a] = sum_j tb[row][j] uq[j][a]
+    cgemm(
+        1, Dll * 2, Dl, Dl, [&](int, int i, int j) { return to_cd(sh.tb[i * SP + j]); },
+        [&](int, int j, int a) { return sh.uq[j * SP + a]; },
+        [&](int, int i, int a, cd v) { sh.ta[i * SP + a] = v; });
     wave_sync();
   }
   if (mode != kGateNone) apply_gate<S, T>(sh, 1, dims(0), lg.get(mode, 0, n, theta, phi, pix));
@@ -639,19 +705,18 @@ __device__ __forceinline__ int svd_split_block(LayerShared<S, T>& sh, int Dl, in
   // padded with zeros to the Jacobi tile's height).
   const int Mk = 2 * Dc, N = 2 * Dr;
   const int MP = jacobi_shape(Mk, N).MP;
-  {
-    const FastDiv fmp(MP), fdc(Dc);
-    for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-      const int col = fmp.q(idx), row = fmp.r(idx);
-      const int t = col >= Dr, b = col - (t ? Dr : 0);
-      cd acc{0.0, 0.0};
-      if (row < Mk) {
-        const int u = row >= Dc, cp = row - (u ? Dc : 0);
-        for (int c = cp; c < Dc; ++c)
-          cfma(acc, cconj(sh.uq[(u * Dc + c) * SP + cp]), to_cd(sh.tb[(c * 2 + (t ^ u)) * SP + b]));
-      }
-      sh.mat[col * LD + row] = acc;
-    }
+  // One product per u; uq holds zeros below each R_u's diagonal, so the sum runs over all c.
+  cgemm(
+      2, Dc, N, Dc, [&](int u, int cp, int c) { return cconj(sh.uq[(u * Dc + c) * SP + cp]); },
+      [&](int u, int c, int col) {
+        const int t = col >= Dr, b = col - (t ? Dr : 0);
+        return to_cd(sh.tb[(c * 2 + (t ^ u)) * SP + b]);
+      },
+      [&](int u, int cp, int col, cd v) { sh.mat[col * LD + u * Dc + cp] = v; });
+  if (MP > Mk) {
+    const int pad = MP - Mk;
+    for (int idx = tid; idx < N * pad; idx += kLayerThreads)
+      sh.mat[(idx / pad) * LD + Mk + idx % pad] = cd{0.0, 0.0};
   }
   wave_sync();
   flags |= jacobi_columns<S, T>(sh, Mk, N);
@@ -678,52 +743,29 @@ __device__ __forceinline__ int svd_split_block(LayerShared<S, T>& sh, int Dl, in
   if (tid == 0 && terr) *terr = (kept + disc > 0.0) ? disc / (kept + disc) : 0.0;
   // X_s[j][c] = sum_{c' <= c} conj(U_K[(s,c')][j]) R_s[c'][c] -> xs[(s*D + j)*Dc + c]
   cd* xs = sh.mat + N * LD;
-  {
-    const FastDiv fdc(Dc), fdd(D);
-    for (int idx = tid; idx < 2 * D * Dc; idx += kLayerThreads) {
-      const int sj = fdc.q(idx), c = fdc.r(idx);
-      const int s_ = sj >= D, j = sj - (s_ ? D : 0);
-      const cd* w = sh.mat + sh.rank[j] * LD + s_ * Dc;
-      cd acc{0.0, 0.0};
-      for (int cp = 0; cp <= c; ++cp) {
-        const cd r = sh.uq[(s_ * Dc + c) * SP + cp];  // conj(R_s[cp][c])
-        const cd u = w[cp];
-        // conj(u) * R = conj(u) * conj(r) = conj(u * r)
-        acc.re = fma(u.re, r.re, fma(-u.im, r.im, acc.re));
-        acc.im = fma(-u.re, r.im, fma(-u.im, r.re, acc.im));
-      }
-      xs[sj * Dc + c] = cscale(acc, sh.isig[j]);
-    }
-  }
+  cgemm(
+      2, D, Dc, Dc, [&](int s_, int j, int cp) { return cconj(sh.mat[sh.rank[j] * LD + s_ * Dc + cp]); },
+      [&](int s_, int cp, int c) { return cconj(sh.uq[(s_ * Dc + c) * SP + cp]); },
+      [&](int s_, int j, int c, cd v) { xs[(s_ * D + j) * Dc + c] = cscale(v, sh.isig[j]); });
   wave_sync();
   // A[k][(a,s)][j] = sum_c' Q_s[a][c'] U_K[(s,c')][j] -> uq
-  {
-    const FastDiv fd(D);
-    for (int idx = tid; idx < 2 * Dl * D; idx += kLayerThreads) {
-      const int row = fd.q(idx), j = fd.r(idx);
-      const int a = row >> 1, s_ = row & 1;
-      const cd* w = sh.mat + sh.rank[j] * LD + s_ * Dc;
-      const cd* q = sh.ta + a * SP + s_ * Dc;
-      cd acc{0.0, 0.0};
-      for (int cp = 0; cp < Dc; ++cp) cfma(acc, q[cp], w[cp]);
-      sh.uq[row * SP + j] = cscale(acc, sh.isig[j]);
-    }
-  }
+  cgemm(
+      2, Dl, D, Dc, [&](int s_, int a, int cp) { return sh.ta[a * SP + s_ * Dc + cp]; },
+      [&](int s_, int cp, int j) { return sh.mat[sh.rank[j] * LD + s_ * Dc + cp]; },
+      [&](int s_, int a, int j, cd v) { sh.uq[(a * 2 + s_) * SP + j] = cscale(v, sh.isig[j]); });
   wave_sync();
-  // centre[j][(t,b)] = sum_s sum_c X_s[j][c] B[c][t XOR s][b] / |sigma_kept| -> ta
-  {
-    const FastDiv f2r(2 * Dr);
-    for (int idx = tid; idx < D * 2 * Dr; idx += kLayerThreads) {
-      const int j = f2r.q(idx), o = f2r.r(idx);
-      const int t = o >= Dr, b = o - (t ? Dr : 0);
-      cd acc{0.0, 0.0};
-      for (int c = 0; c < Dc; ++c) {
-        cfma(acc, xs[j * Dc + c], to_cd(sh.tb[(c * 2 + t) * SP + b]));
-        cfma(acc, xs[(D + j) * Dc + c], to_cd(sh.tb[(c * 2 + (t ^ 1)) * SP + b]));
-      }
-      sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
-    }
-  }
+  // centre[j][(t,b)] = sum_s sum_c X_s[j][c] B[c][t XOR s][b] / |sigma_kept| -> ta, summation
+  // index k = 2c + s
+  cgemm(
+      1, D, 2 * Dr, 2 * Dc, [&](int, int j, int k) { return xs[((k & 1) * D + j) * Dc + (k >> 1)]; },
+      [&](int, int k, int o) {
+        const int t = o >= Dr, b = o - (t ? Dr : 0);
+        return to_cd(sh.tb[((k >> 1) * 2 + (t ^ (k & 1))) * SP + b]);
+      },
+      [&](int, int j, int o, cd v) {
+        const int t = o >= Dr, b = o - (t ? Dr : 0);
+        sh.ta[(j * 2 + t) * SP + b] = cscale(v, inv_norm);
+      });
   wave_sync();
   return flags;
 }
@@ -787,17 +829,18 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
     const int M = 2 * Dl, N = 2 * Dr;
     const int MP = jacobi_shape(M, N).MP;
     // Theta'[(a,s),(t,b)] = sum_c A[k][a,s,c] A[k+1][c, t XOR (cx s), b]   (CNOT control k).
-    {
-      const FastDiv fmp(MP), fdr(Dr);
-      for (int idx = tid; idx < N * MP; idx += kLayerThreads) {
-        const int col = fmp.q(idx), row = fmp.r(idx);
-        const int t = col >= Dr, b = col - (t ? Dr : 0), s_ = row & 1;
-        cd acc{0.0, 0.0};
-        if (row < M)
-          for (int c = 0; c < Dc; ++c)
-            cfma(acc, sh.ta[row * SP + c], to_cd(sh.tb[(c * 2 + (t ^ (s_ & cx))) * SP + b]));
-        sh.mat[col * LD + row] = acc;
-      }
+    // One product per s (rows (a, s) of Theta' = a*2 + s); the tile's padding rows are zero.
+    cgemm(
+        2, Dl, N, Dc, [&](int s_, int a, int c) { return sh.ta[(a * 2 + s_) * SP + c]; },
+        [&](int s_, int c, int col) {
+          const int t = col >= Dr, b = col - (t ? Dr : 0);
+          return to_cd(sh.tb[(c * 2 + (t ^ (s_ & cx))) * SP + b]);
+        },
+        [&](int s_, int a, int col, cd v) { sh.mat[col * LD + a * 2 + s_] = v; });
+    if (MP > M) {
+      const int pad = MP - M;
+      for (int idx = tid; idx < N * pad; idx += kLayerThreads)
+        sh.mat[(idx / pad) * LD + M + idx % pad] = cd{0.0, 0.0};
     }
     wave_sync();
     if (exact_qr && D == (M < N ? M : N)) {
@@ -853,32 +896,23 @@ __device__ __forceinline__ int cnot_sweep(LayerShared<S, T>& sh, T* st, int n, B
     pend_dl = Dl;
     pend_d = D;
     // X_s = U_s^H A_s  ->  mat[(s*S + j)*SP + c]
-    {
-      const FastDiv fdc(Dc), fdd(D);
-      for (int idx = tid; idx < 2 * D * Dc; idx += kLayerThreads) {
-        const int sj = fdc.q(idx), c = fdc.r(idx);
-        const int s_ = sj >= D, j = sj - (s_ ? D : 0);
-        cd acc{0.0, 0.0};
-        for (int a = 0; a < Dl; ++a)
-          cfmac(acc, sh.uq[(a * 2 + s_) * SP + j], sh.ta[(a * 2 + s_) * SP + c]);
-        sh.mat[(s_ * S + j) * SP + c] = acc;
-      }
-    }
+    cgemm(
+        2, D, Dc, Dl, [&](int s_, int j, int a) { return cconj(sh.uq[(a * 2 + s_) * SP + j]); },
+        [&](int s_, int a, int c) { return sh.ta[(a * 2 + s_) * SP + c]; },
+        [&](int s_, int j, int c, cd v) { sh.mat[(s_ * S + j) * SP + c] = v; });
     wave_sync();
-    // New centre S V^H = U^H Theta' / |sigma_kept|  ->  ta[(j*2+t)*SP + b]
-    {
-      const FastDiv f2r(2 * Dr);
-      for (int idx = tid; idx < D * 2 * Dr; idx += kLayerThreads) {
-        const int j = f2r.q(idx), o = f2r.r(idx);
-        const int t = o >= Dr, b = o - (t ? Dr : 0);
-        cd acc{0.0, 0.0};
-        for (int c = 0; c < Dc; ++c) {
-          cfma(acc, sh.mat[j * SP + c], to_cd(sh.tb[(c * 2 + t) * SP + b]));
-          cfma(acc, sh.mat[(S + j) * SP + c], to_cd(sh.tb[(c * 2 + (t ^ cx)) * SP + b]));
-        }
-        sh.ta[(j * 2 + t) * SP + b] = cscale(acc, inv_norm);
-      }
-    }
+    // New centre S V^H = U^H Theta' / |sigma_kept|  ->  ta[(j*2+t)*SP + b]; summation index
+    // k = 2c + s over both X_s.
+    cgemm(
+        1, D, 2 * Dr, 2 * Dc, [&](int, int j, int k) { return sh.mat[((k & 1) * S + j) * SP + (k >> 1)]; },
+        [&](int, int k, int o) {
+          const int t = o >= Dr, b = o - (t ? Dr : 0);
+          return to_cd(sh.tb[((k >> 1) * 2 + (t ^ ((k & 1) & cx))) * SP + b]);
+        },
+        [&](int, int j, int o, cd v) {
+          const int t = o >= Dr, b = o - (t ? Dr : 0);
+          sh.ta[(j * 2 + t) * SP + b] = cscale(v, inv_norm);
+        });
     wave_sync();
   }
   if (pend_k >= 0) store_tensor<S, T>(st + (size_t)pend_k * SLOT, sh.uq, pend_dl, pend_d);
