@@ -118,10 +118,14 @@ __device__ __forceinline__ double dpp_mov_d(double v) {
 // makes x'^H y' = 0; c = 1/sqrt(1 + tau^2 |g|^2).  The update is unitary whenever
 // c^2 + |sig|^2 = 1, whatever tau is, so tau comes from the hardware estimates of 1/sqrt and
 // 1/x (relative error ~2^-22: the pair is then orthogonal to that fraction of |g|, which the
-// next sweep removes) and only c is refined to full precision by two Newton steps.
+// next sweep removes) and only c is refined by NR Newton steps: two reach full precision; one
+// leaves c^2 + |sig|^2 = 1 to ~1e-13, which only rescales the pair's columns (an update that
+// is a scalar multiple of a unitary one keeps their orthogonality), enough where the factors
+// are stored in FP32.
 struct JacobiRot {
   double c, sr, si;  // sig = sr + i si
 };
+template <int NR = 2>
 __device__ __forceinline__ JacobiRot jacobi_rot(double a, double b, double gr, double gi,
                                                 double ag2) {
   const double d = 0.5 * (b - a);
@@ -131,8 +135,8 @@ __device__ __forceinline__ JacobiRot jacobi_rot(double a, double b, double gr, d
   const double u = fma(tau * tau, ag2, 1.0);
   const double h = 0.5 * u;
   double c = __builtin_amdgcn_rsq(u);
-  c = c * fma(-h * c, c, 1.5);
-  c = c * fma(-h * c, c, 1.5);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) c = c * fma(-h * c, c, 1.5);
   const double ct = c * tau;
   return {c, ct * gr, -ct * gi};
 }

@@ -19,15 +19,16 @@ namespace anomps {
 constexpr int kLayerThreads = 64;
 constexpr int kMaxSweeps = 30;
 
-// Orders LDS accesses across the lanes of a one-wavefront workgroup: waits for the wave's own
-// LDS operations and keeps the compiler from moving memory accesses across, but leaves its
-// global loads in flight (a __syncthreads fences global memory too, i.e. waits for every
-// outstanding load and store, which would undo the prefetches of the next site tensor).  A
-// wavefront's LDS operations execute in issue order, so this is all the ordering its lanes
-// need among themselves.
+// Orders LDS accesses across the lanes of a one-wavefront workgroup.  The LDS executes one
+// wavefront's instructions in issue order (a read issued after a write sees the write, from
+// any lane), so the only ordering the lanes need among themselves is the program order of the
+// LDS instructions: this keeps the compiler from moving memory accesses across and waits for
+// nothing (the compiler waits for a read's data where it is used).  Global loads stay in flight
+// (a __syncthreads waits for every outstanding load and store, which would undo the prefetches
+// of the next site tensor).
 __device__ __forceinline__ void wave_sync() {
   static_assert(kLayerThreads == 64, "one wavefront per workgroup");
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  asm volatile("" ::: "memory");
 }
 
 // ------------------------------------------------------------------------------- encode
@@ -277,7 +278,7 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
       if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
         rotated = 1;
         big |= ag2 > kBig * ab;
-        const JacobiRot jr = jacobi_rot(a, bb, gr, gi, ag2);
+        const JacobiRot jr = jacobi_rot<std::is_same<T, float>::value ? 1 : 2>(a, bb, gr, gi, ag2);
 #pragma unroll
         for (int tt = 0; tt < R; ++tt) {
           const int rr = lt + tt * TM;
