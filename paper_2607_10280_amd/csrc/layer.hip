@@ -110,12 +110,23 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps (full FP64 precision).
-__device__ __forceinline__ double rsqrt_full(double x) {
+// 1/sqrt(x) for x > 0: hardware estimate (relative error ~2^-22) refined by NR Newton steps;
+// two reach full FP64 precision, one ~1e-13.
+template <int NR = 2>
+__device__ __forceinline__ double rsqrt_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);
   const double h = 0.5 * x;
-  r = r * fma(-h * r, r, 1.5);
-  r = r * fma(-h * r, r, 1.5);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_full(double x) { return rsqrt_nr<2>(x); }
+// 1/x likewise.
+template <int NR = 2>
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < NR; ++i) r = fma(r, fma(-x, r, 1.0), r);
   return r;
 }
 
@@ -182,9 +193,15 @@ __device__ __forceinline__ void valu_cgemm(int NB, int M, int N, int K, FA a, FB
   for (int idx = threadIdx.x; idx < NB * mn; idx += kLayerThreads) {
     const int b = fmn.q(idx), rem = fmn.r(idx);
     const int i = fn.q(rem), j = fn.r(rem);
-    cd acc{0.0, 0.0};
-    for (int k = 0; k < K; ++k) cfma(acc, a(b, i, k), bm(b, k, j));
-    out(b, i, j, acc);
+    // even and odd k in two accumulators: half the dependent chain
+    cd acc0{0.0, 0.0}, acc1{0.0, 0.0};
+    int k = 0;
+    for (; k + 2 <= K; k += 2) {
+      cfma(acc0, a(b, i, k), bm(b, k, j));
+      cfma(acc1, a(b, i, k + 1), bm(b, k + 1, j));
+    }
+    if (k < K) cfma(acc0, a(b, i, k), bm(b, k, j));
+    out(b, i, j, cd{acc0.re + acc1.re, acc0.im + acc1.im});
   }
 }
 
@@ -388,14 +405,17 @@ __device__ __forceinline__ void householder_lq(LayerShared<S, T>& sh, int M, int
       cd beta{dr, di}, v0{dr, di};
       double coef = 0.0;
       if (a2 > tiny2) {
-        const double alpha = a2 * rsqrt_full(a2);
+        // One Newton step where the factors are stored in FP32: the reflector is then unitary
+        // and the zeroed entries vanish to ~1e-13 relative, far below the storage rounding.
+        constexpr int NR = std::is_same<T, float>::value ? 1 : 2;
+        const double alpha = a2 * rsqrt_nr<NR>(a2);
         const double d2 = fma(dr, dr, di * di);
-        const double rd = d2 > 0.0 ? rsqrt_full(d2) : 0.0;
+        const double rd = d2 > 0.0 ? rsqrt_nr<NR>(d2) : 0.0;
         const double ad = d2 * rd;                          // |a_jj|
         const cd u = d2 > 0.0 ? cd{dr * rd, di * rd} : cd{1.0, 0.0};
         beta = cd{-u.re * alpha, -u.im * alpha};
         v0 = cd{u.re * (ad + alpha), u.im * (ad + alpha)};
-        coef = rcp_full(alpha * (alpha + ad));              // 2 / |v|^2
+        coef = rcp_nr<NR>(alpha * (alpha + ad));            // 2 / |v|^2
       }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
