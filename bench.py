@@ -39,8 +39,8 @@ MEASURED_TRAFFIC = {
     # one k_layer launch (one layer of the canonical sweep + Jacobi SVD ladder), averaged over
     # the four layers of the headline
     "layers_svd": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-                   "sha1": "2d8430dff89b080a84dbdf49ae4a3f5de3b1752e",
-                   "bytes": (2 * 37060.0 + 73840.0) * 1024},
+                   "sha1": "fb93050a1d4ef8fe5ece4c4816d2369f500b8119",
+                   "bytes": (2 * 38150.0 + 73470.0) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16, blocks of 64 images)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
                 "sha1": "b5a5217119d97090ec7d1394cafbc6362dcc893d",
