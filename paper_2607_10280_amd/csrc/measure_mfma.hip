@@ -372,22 +372,12 @@ __device__ __forceinline__ void env16_image(const typename MmaReal<MODE>::type* 
 }
 
 // ------------------------------------------------------------------------- pairs
-__device__ __forceinline__ float pauli_re(int a, int r, int c, bool want_im) {
-  // (P_a)[r][c] real or imaginary part
-  switch (a) {
-    case 0: return want_im ? 0.f : (float)(r == c);
-    case 1: return want_im ? 0.f : (float)(r != c);
-    case 2: return want_im ? ((r == c) ? 0.f : (r == 0 ? -1.f : 1.f)) : 0.f;
-    default: return want_im ? 0.f : ((r == c) ? (r == 0 ? 1.f : -1.f) : 0.f);
-  }
-}
-
 template <typename C>
 __device__ __forceinline__ C cmul_c(C a, C b) { return C{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 
 // Operands fetched one step ahead: the site (column form to carry through it and to open,
 // row form to close) and, at the open, L_i.  R_{j+1} and L_j are read at the close itself:
-// prefetching them too costs a register spill at three waves per SIMD, which is slower.
+// prefetching them too made the pair kernel slower (more registers, fewer waves in flight).
 template <typename R>
 struct PairStep {
   SiteOps<R> s;
@@ -566,21 +556,29 @@ __device__ __forceinline__ void pairs16_image(const typename MmaReal<MODE>::type
                          C{e01.re, -e01.im}, C{d11, 0}, e12, e13,
                          C{e02.re, -e02.im}, C{e12.re, -e12.im}, C{d22, 0}, e23,
                          C{e03.re, -e03.im}, C{e13.re, -e13.im}, C{e23.re, -e23.im}, C{d33, 0}};
-      if (l < 15) {
-        // <P_a (x) P_c> = sum_{s,t,s',t'} rho[(s,t),(s',t')] P_a[s'][s] P_c[t'][t]
-        const int al = l + 1, pa_ = al >> 2, pc = al & 3;
+      // <P_a (x) P_c> = sum_{s,t,s',t'} rho[(s,t),(s',t')] P_a[s'][s] P_c[t'][t].  A Pauli
+      // matrix has one entry per column: P[s'][s] = phi(s) for s' = s XOR x (x = 1 for X and Y),
+      // phi = 1 (I, X), i (-1)^s (Y), (-1)^s (Z); so each expectation is four entries of rho
+      // times a phase in {1, i, -1, -i}, fixed at compile time.  Every lane evaluates all 15
+      // (the entries are the same in all lanes) and lane l keeps number l.
+      R val = 0;
+#pragma unroll
+      for (int o = 0; o < 15; ++o) {
+        const int pa_ = (o + 1) >> 2, pc = (o + 1) & 3;
+        const int xa = (pa_ == 1 || pa_ == 2), xc = (pc == 1 || pc == 2);
         R acc = 0;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int s = e >> 3, t = (e >> 2) & 1, sp = (e >> 1) & 1, tp = e & 1;
-          const R ar = pauli_re(pa_, sp, s, false), ai = pauli_re(pa_, sp, s, true);
-          const R cr = pauli_re(pc, tp, t, false), ci = pauli_re(pc, tp, t, true);
-          const R wr = ar * cr - ai * ci, wi = ar * ci + ai * cr;
-          const C rv = rho[(s * 2 + t) * 4 + sp * 2 + tp];
-          acc += rv.re * wr - rv.im * wi;
+        for (int st = 0; st < 4; ++st) {
+          const int s = st >> 1, t = st & 1;
+          const C z = rho[(s * 2 + t) * 4 + (s ^ xa) * 2 + (t ^ xc)];
+          const int ipow = (pa_ == 2) + (pc == 2);
+          const bool neg = (((pa_ >= 2) && s) != ((pc >= 2) && t)) != (ipow == 2);
+          const R v = (ipow == 1) ? -z.im : z.re;  // Re(z i^ipow) up to the sign
+          acc += neg ? -v : v;
         }
-        out[(size_t)uniform_int(tq[x]) * 15 + l] = acc;
+        val = (l == o) ? acc : val;
       }
+      if (l < 15) out[(size_t)uniform_int(tq[x]) * 15 + l] = val;
     }
     if (kind == 1) ++x;
     else if (kind == 0) cur = site + 1;
