@@ -240,7 +240,8 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
 // sweep.  A team of T lanes owns a pair; each lane holds R rows of both columns in registers,
 // the team reduces |x|^2, |y|^2 and x^H y with DPP row moves, and every lane of the team
 // evaluates the same rotation.  A pair is rotated when |x^H y|^2 > tol^2 |x|^2 |y|^2 with
-// tol = M eps; columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2 count as numerically zero.
+// tol = M eps (at least 1e-7 for FP32 storage); columns with |x|^2 <= tiny2 = 1e-30 |A|_F^2
+// count as numerically zero.
 // On return sig2[c] = |w_c|^2 for c < N.  Returns kImgNoConvergence if the sweep limit hit.
 template <int S, typename T, int NP, int R>
 __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) {
@@ -260,7 +261,10 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
   f = block_sum(f, sh.red);
   const double tiny2 = 1e-30 * f;
   if (tid == 0) sh.tiny2 = tiny2;
-  const double tol = (double)M * 2.220446049250313e-16;
+  // Factors stored in FP32 (rounding 6e-8) gain nothing from rotating pairs closer than 1e-7
+  // to orthogonal: the sweep that confirms convergence then rotates no pair at all.
+  const double tol = std::is_same<T, float>::value ? fmax((double)M * 2.220446049250313e-16, 1e-7)
+                                                   : (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   constexpr double kBig = std::is_same<T, float>::value ? 1e-8 : 1e-16;
   bool converged = (N < 2);
