@@ -266,7 +266,7 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
   const double tol = std::is_same<T, float>::value ? fmax((double)M * 2.220446049250313e-16, 1e-7)
                                                    : (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
-  constexpr double kBig = std::is_same<T, float>::value ? 1e-8 : 1e-16;
+  constexpr double kBig = std::is_same<T, float>::value ? 1e-7 : 1e-16;
   bool converged = (N < 2);
   int sweep = 0;
   for (; !converged && sweep < kMaxSweeps; ++sweep) {
@@ -315,8 +315,8 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
     // Converged when nothing was rotated, or when every rotated pair of this sweep was already
     // close to orthogonal: one-sided Jacobi converges quadratically, so a sweep whose pairs
     // were all within delta of orthogonal leaves them within ~delta^2.  delta = 1e-8 (columns
-    // orthogonal to ~1e-16) for FP64 storage; 1e-4 (~1e-8, below the 2^-24 rounding of the
-    // stored tensors) for FP32 storage.
+    // orthogonal to ~1e-16) for FP64 storage; 3.2e-4 for FP32 storage (~1e-7, the floor below
+    // which pairs are not rotated, about the 2^-24 rounding of the stored tensors).
     converged = __ballot(rotated & big) == 0;
   }
   // sig2[c] = |w_c|^2: each team reduces one column at a time
