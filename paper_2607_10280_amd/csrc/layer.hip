@@ -85,6 +85,20 @@ __device__ __forceinline__ double team_sum(double v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+// team_sum in FP32.
+template <int T>
+__device__ __forceinline__ float team_sum_f(float v) {
+  if constexpr (T >= 16) v += dpp_mov_f<0x140>(v);  // row_mirror
+  if constexpr (T >= 8) v += dpp_mov_f<0x141>(v);   // row_half_mirror
+  if constexpr (T >= 4) v += dpp_mov_f<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (T >= 2) v += dpp_mov_f<0xB1>(v);    // quad_perm [1,0,3,2]
+  return v;
+}
+
 // Sum over the wavefront, the same value in every lane: the four DPP rows are summed inside
 // (team_sum), and their sums are read as scalars and added in a fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -290,10 +304,20 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
         a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
         bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
       }
-      a = team_sum<TM>(a);
-      bb = team_sum<TM>(bb);
-      gr = team_sum<TM>(gr);
-      gi = team_sum<TM>(gi);
+      if constexpr (std::is_same<T, float>::value) {
+        // FP32 storage: the team sums in FP32 (one lane move per step instead of two).  The
+        // rotation stays exactly unitary (c and sigma come from the same sums) and the columns
+        // are rotated in FP64; only the angle is known to ~1e-7, the rotation floor.
+        a = team_sum_f<TM>((float)a);
+        bb = team_sum_f<TM>((float)bb);
+        gr = team_sum_f<TM>((float)gr);
+        gi = team_sum_f<TM>((float)gi);
+      } else {
+        a = team_sum<TM>(a);
+        bb = team_sum<TM>(bb);
+        gr = team_sum<TM>(gr);
+        gi = team_sum<TM>(gi);
+      }
       const double ag2 = fma(gr, gr, gi * gi);
       const double ab = a * bb;
       if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
