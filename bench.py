@@ -39,12 +39,12 @@ MEASURED_TRAFFIC = {
     # one k_layer launch (one layer of the canonical sweep + Jacobi SVD ladder), averaged over
     # the four layers of the headline
     "layers_svd": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-                   "sha1": "de9960c300ddf91ba1fcb5915b44027b0314b9de",
-                   "bytes": (2 * 39000.0 + 73750.0) * 1024},
+                   "sha1": "a2c41f295ca2413b7c2de320f2c1cf6d42e6d95d",
+                   "bytes": (2 * 38040.0 + 73960.0) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16, blocks of 64 images)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
                 "sha1": "e6a3d207a6a8c958fbc5c4e8437ff6e42cdd7f1f",
-                "bytes": (2 * (194600.0 + 224800.0) + (204800.0 + 5626.0)) * 1024},
+                "bytes": (2 * (194600.0 + 222900.0) + (204800.0 + 5631.0)) * 1024},
 }
 
 
