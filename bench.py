@@ -39,7 +39,7 @@ MEASURED_TRAFFIC = {
     # one k_layer launch (one layer of the canonical sweep + Jacobi SVD ladder), averaged over
     # the four layers of the headline
     "layers_svd": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-                   "sha1": "a2c41f295ca2413b7c2de320f2c1cf6d42e6d95d",
+                   "sha1": "ce53bb4a777e53c8a75cd00036420e9844d7a64b",
                    "bytes": (2 * 38040.0 + 73960.0) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16, blocks of 64 images)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",

@@ -305,9 +305,10 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
         bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
       }
       if constexpr (std::is_same<T, float>::value) {
-        // FP32 storage: the team sums in FP32 (one lane move per step instead of two).  The
-        // rotation stays exactly unitary (c and sigma come from the same sums) and the columns
-        // are rotated in FP64; only the angle is known to ~1e-7, the rotation floor.
+        // FP32 storage: the team sums in FP32, each step one DPP-modified add instead of two
+        // lane moves and an FP64 add.  The rotation stays exactly unitary (c and sigma come
+        // from the same sums) and the columns are rotated in FP64; only the angle is known to
+        // ~1e-7, the rotation floor.
         a = team_sum_f<TM>((float)a);
         bb = team_sum_f<TM>((float)bb);
         gr = team_sum_f<TM>((float)gr);
