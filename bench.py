@@ -39,12 +39,12 @@ MEASURED_TRAFFIC = {
     # one k_layer launch (one layer of the canonical sweep + Jacobi SVD ladder), averaged over
     # the four layers of the headline
     "layers_svd": {"source": "paper_2607_10280_amd/csrc/layer.hip",
-                   "sha1": "ce53bb4a777e53c8a75cd00036420e9844d7a64b",
-                   "bytes": (2 * 38040.0 + 73960.0) * 1024},
+                   "sha1": "3b8824bf3b21012db511018fbf8ba81a5c2f76cb",
+                   "bytes": (2 * 36810.0 + 73450.0) * 1024},
     # one measurement call: k_env16 + k_pairs16 (complex64, slot 16, blocks of 64 images)
     "measure": {"source": "paper_2607_10280_amd/csrc/measure_mfma.hip",
                 "sha1": "e6a3d207a6a8c958fbc5c4e8437ff6e42cdd7f1f",
-                "bytes": (2 * (194600.0 + 222900.0) + (204800.0 + 5631.0)) * 1024},
+                "bytes": (2 * (194600.0 + 223460.0) + (204830.0 + 5617.0)) * 1024},
 }
 
 

@@ -249,7 +249,8 @@ __host__ __device__ inline JShape jacobi_shape(int M, int N) {
   return j;
 }
 
-// One-sided (Hestenes) Jacobi on the N columns of `mat` (rows [M, MP) must be zero) in FP64.
+// One-sided (Hestenes) Jacobi on the N columns of `mat` (rows [M, MP) must be zero; columns
+// [N, NP) are overwritten with zeros) in FP64.
 // Column pairs follow the round-robin tournament: NP-1 rounds of NP/2 disjoint pairs per
 // sweep.  A team of T lanes owns a pair; each lane holds R rows of both columns in registers,
 // the team reduces |x|^2, |y|^2 and x^H y with DPP row moves, and every lane of the team
@@ -272,6 +273,10 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
     const cd v = sh.mat[(idx / MP) * LD + (idx % MP)];
     f = fma(v.re, v.re, fma(v.im, v.im, f));
   }
+  // Padding columns [N, NP) are set to zero: a pair with one of them never passes the
+  // negligible-column test, so the rounds need no column-range test.
+  for (int idx = tid; idx < (NP - N) * MP; idx += kLayerThreads)
+    sh.mat[(N + idx / MP) * LD + (idx % MP)] = cd{0.0, 0.0};
   f = block_sum(f, sh.red);
   const double tiny2 = 1e-30 * f;
   if (tid == 0) sh.tiny2 = tiny2;
@@ -281,29 +286,41 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
                                                    : (double)M * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   constexpr double kBig = std::is_same<T, float>::value ? 1e-7 : 1e-16;
+  // byte offsets into mat: kRow per row, kCol per column
+  constexpr int kRow = (int)sizeof(cd), kCol = LD * kRow;
+  char* const base = reinterpret_cast<char*>(sh.mat);
+  const int inc_i = (active && q > 0) ? kCol : 0, inc_j = active ? kCol : 0;
+  const int wrap = NP * kCol + lt * kRow, first = kCol + lt * kRow;
+  // lanes without a pair never pass the negligible-column test
+  const double tiny2_l = active ? tiny2 : __builtin_huge_val();
   bool converged = (N < 2);
   int sweep = 0;
   for (; !converged && sweep < kMaxSweeps; ++sweep) {
-    int rotated = 0, big = 0;
+    int big = 0;
     // Round-robin positions: pair q = (pos(q), pos(NP-1-q)), pos(0) = 0 and pos(i) =
-    // 1 + ((i - 1 + r) mod (NP - 1)); advanced incrementally from round to round.
-    int ci = (q == 0) ? 0 : q, cj = NP - 1 - q;
+    // 1 + ((i - 1 + r) mod (NP - 1)), advanced from round to round as byte offsets oi, oj of
+    // the lane's first rows of the two columns: + one column, from column NP back to column 1
+    // (column 0 stays; lanes without a pair stay on column 0 and never store).  The next
+    // offsets are computed early in each round, off the path from the last store to the next
+    // round's loads.
+    int oi = ((q == 0 || !active) ? 0 : q) * kCol + lt * kRow;
+    int oj = (active ? NP - 1 - q : 0) * kCol + lt * kRow;
     for (int r = 0; r < NP - 1; ++r) {
-      const int ci_ = active ? ci : 0, cj_ = active ? cj : 0;
-      const bool valid = active && ci < N && cj < N;
       cd x[R], y[R];
       double gr = 0.0, gi = 0.0;
       double a = 0.0, bb = 0.0;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const int rr = lt + t * TM;
-        x[t] = sh.mat[ci_ * LD + rr];
-        y[t] = sh.mat[cj_ * LD + rr];
+        x[t] = *reinterpret_cast<const cd*>(base + oi + t * TM * kRow);
+        y[t] = *reinterpret_cast<const cd*>(base + oj + t * TM * kRow);
         gr = fma(x[t].re, y[t].re, fma(x[t].im, y[t].im, gr));
         gi = fma(x[t].re, y[t].im, fma(-x[t].im, y[t].re, gi));
         a = fma(x[t].re, x[t].re, fma(x[t].im, x[t].im, a));
         bb = fma(y[t].re, y[t].re, fma(y[t].im, y[t].im, bb));
       }
+      int oi_n = oi + inc_i, oj_n = oj + inc_j;
+      oi_n = (oi_n == wrap) ? first : oi_n;
+      oj_n = (oj_n == wrap) ? first : oj_n;
       if constexpr (std::is_same<T, float>::value) {
         // FP32 storage: the team sums in FP32, each step one DPP-modified add instead of two
         // lane moves and an FP64 add.  The rotation stays exactly unitary (c and sigma come
@@ -321,28 +338,29 @@ __device__ __forceinline__ int jacobi_tile(LayerShared<S, T>& sh, int M, int N) 
       }
       const double ag2 = fma(gr, gr, gi * gi);
       const double ab = a * bb;
-      if (valid && a > tiny2 && bb > tiny2 && ag2 > tol2 * ab) {
-        rotated = 1;
-        big |= ag2 > kBig * ab;
+      // the next offsets are computed here, ahead of the test
+      asm volatile("" ::"v"(oi_n), "v"(oj_n));
+      if (fmin(a, bb) > tiny2_l && ag2 > tol2 * ab) {
+        if (ag2 > kBig * ab) big = 1;
         const JacobiRot jr = jacobi_rot<std::is_same<T, float>::value ? 1 : 2>(a, bb, gr, gi, ag2);
 #pragma unroll
         for (int tt = 0; tt < R; ++tt) {
-          const int rr = lt + tt * TM;
           jacobi_apply(jr, x[tt], y[tt]);
-          sh.mat[ci * LD + rr] = x[tt];
-          sh.mat[cj * LD + rr] = y[tt];
+          *reinterpret_cast<cd*>(base + oi + tt * TM * kRow) = x[tt];
+          *reinterpret_cast<cd*>(base + oj + tt * TM * kRow) = y[tt];
         }
       }
       wave_sync();
-      if (q > 0) ci = (ci == NP - 1) ? 1 : ci + 1;
-      cj = (cj == NP - 1) ? 1 : cj + 1;
+      oi = oi_n;
+      oj = oj_n;
     }
     // Converged when nothing was rotated, or when every rotated pair of this sweep was already
     // close to orthogonal: one-sided Jacobi converges quadratically, so a sweep whose pairs
     // were all within delta of orthogonal leaves them within ~delta^2.  delta = 1e-8 (columns
     // orthogonal to ~1e-16) for FP64 storage; 3.2e-4 for FP32 storage (~1e-7, the floor below
-    // which pairs are not rotated, about the 2^-24 rounding of the stored tensors).
-    converged = __ballot(rotated & big) == 0;
+    // which pairs are not rotated, about the 2^-24 rounding of the stored tensors).  A lane
+    // sets big only for a pair it rotates.
+    converged = __ballot(big) == 0;
   }
   // sig2[c] = |w_c|^2: each team reduces one column at a time
 #pragma unroll
